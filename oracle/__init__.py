@@ -1,0 +1,204 @@
+"""Plain CPU oracle for exact DeepWalk / node2vec walk generation.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  The GPU library
+(``paper_2110_06196_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``n2v_oracle.c`` (single-threaded, plain loops); this
+module only compiles it with gcc and marshals numpy arrays through ctypes.
+Each C function cites the passage of the paper it follows (Methods, "First and
+second-order RW-based embedding methods", Eq. 1-3 and the four sampling steps
+of "Efficient sampling for Node2Vec RWs").
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "n2v_oracle.c")
+_LIB = os.path.join(_HERE, "libn2v_oracle.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSORTED, ERR_OVERFLOW = 0, -1, -2, -3
+FIRST_ORDER, NODE2VEC = 0, 1
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain -O2, no vectorisation tricks needed)."""
+    tmp = _LIB + f".tmp{os.getpid()}"
+    subprocess.check_call(
+        ["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+    )
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _p(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t)) if a is not None else None
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build()
+            L = ctypes.CDLL(_LIB)
+            u64p = ctypes.POINTER(ctypes.c_uint64)
+            u32p = ctypes.POINTER(ctypes.c_uint32)
+            i32p = ctypes.POINTER(ctypes.c_int32)
+            i64p = ctypes.POINTER(ctypes.c_int64)
+            L.n2vo_q16.argtypes = [ctypes.c_double, u32p]
+            L.n2vo_q16.restype = ctypes.c_int
+            L.n2vo_philox4x32_10.argtypes = [u32p, u32p, u32p]
+            L.n2vo_philox4x32_10.restype = None
+            L.n2vo_draw64.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64]
+            L.n2vo_draw64.restype = ctypes.c_uint64
+            L.n2vo_scale.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+            L.n2vo_scale.restype = ctypes.c_uint64
+            L.n2vo_validate.argtypes = [u64p, ctypes.c_int64, i32p, ctypes.c_uint64]
+            L.n2vo_validate.restype = ctypes.c_int
+            L.n2vo_stats.argtypes = [u64p, ctypes.c_int64, u32p, u64p, u64p]
+            L.n2vo_stats.restype = None
+            L.n2vo_step_weights.argtypes = [u64p, i32p, u32p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, u64p]
+            L.n2vo_step_weights.restype = ctypes.c_int64
+            L.n2vo_select.argtypes = [u64p, ctypes.c_int64, ctypes.c_uint64]
+            L.n2vo_select.restype = ctypes.c_int64
+            common = [u64p, ctypes.c_int64, i32p, ctypes.c_uint64, u32p, i32p, ctypes.c_int64,
+                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, ctypes.c_double,
+                      ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64]
+            L.n2vo_walks_subset.argtypes = common + [i64p, ctypes.c_int64, i32p, i32p]
+            L.n2vo_walks_subset.restype = ctypes.c_int
+            L.n2vo_walks.argtypes = common + [i32p, i32p]
+            L.n2vo_walks.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle status {code}")
+        self.code = code
+
+
+def _csr(offsets, dst, weights):
+    O = np.ascontiguousarray(offsets, dtype=np.uint64)
+    D = np.ascontiguousarray(dst, dtype=np.int32)
+    W = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint32)
+    return O, D, W
+
+
+def q16(x: float) -> int:
+    out = ctypes.c_uint32(0)
+    rc = lib().n2vo_q16(float(x), ctypes.byref(out))
+    if rc != OK:
+        raise OracleError(rc)
+    return int(out.value)
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().n2vo_philox4x32_10(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32), _p(o, ctypes.c_uint32))
+    return o
+
+
+def draw64(seed: int, step: int, wid: int) -> int:
+    return int(lib().n2vo_draw64(seed, step, wid))
+
+
+def scale(r64: int, total: int) -> int:
+    return int(lib().n2vo_scale(r64, total))
+
+
+def validate(offsets, dst) -> int:
+    O, D, _ = _csr(offsets, dst, None)
+    n = O.size - 1
+    return int(lib().n2vo_validate(_p(O, ctypes.c_uint64), n, _p(D, ctypes.c_int32), D.size))
+
+
+def stats(offsets, weights=None):
+    O = np.ascontiguousarray(offsets, dtype=np.uint64)
+    W = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint32)
+    md, ms = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    lib().n2vo_stats(_p(O, ctypes.c_uint64), O.size - 1, _p(W, ctypes.c_uint32),
+                     ctypes.byref(md), ctypes.byref(ms))
+    return int(md.value), int(ms.value)
+
+
+def step_weights(offsets, dst, weights, t: int, v: int, second_order: bool, P16: int, Q16: int):
+    O, D, W = _csr(offsets, dst, weights)
+    d = int(O[v + 1] - O[v])
+    b = np.zeros(max(d, 1), dtype=np.uint64)
+    got = lib().n2vo_step_weights(_p(O, ctypes.c_uint64), _p(D, ctypes.c_int32), _p(W, ctypes.c_uint32),
+                                  t, v, int(second_order), P16, Q16, _p(b, ctypes.c_uint64))
+    assert got == d
+    return b[:d]
+
+
+def select(b, T: int) -> int:
+    bb = np.ascontiguousarray(b, dtype=np.uint64)
+    return int(lib().n2vo_select(_p(bb, ctypes.c_uint64), bb.size, T))
+
+
+def walks(offsets, dst, weights, starts, walks_per_start: int, walk_len: int, kind: int,
+          p: float = 1.0, q: float = 1.0, seed: int = 0, walk_id_base: int = 0, rows=None):
+    """Run the oracle.  rows: None for all walks, else the walk-row indices to produce.
+
+    Returns (Y int32[nrows][walk_len], lens int32[nrows])."""
+    O, D, W = _csr(offsets, dst, weights)
+    S = np.ascontiguousarray(starts, dtype=np.int32)
+    n = O.size - 1
+    args = (_p(O, ctypes.c_uint64), n, _p(D, ctypes.c_int32), D.size, _p(W, ctypes.c_uint32),
+            _p(S, ctypes.c_int32), S.size, walks_per_start, walk_len, kind, float(p), float(q),
+            seed, walk_id_base)
+    if rows is None:
+        nw = S.size * walks_per_start
+        Y = np.empty((nw, walk_len), dtype=np.int32)
+        lens = np.empty(nw, dtype=np.int32)
+        rc = lib().n2vo_walks(*args, _p(Y, ctypes.c_int32), _p(lens, ctypes.c_int32))
+    else:
+        idx = np.ascontiguousarray(rows, dtype=np.int64)
+        Y = np.empty((idx.size, walk_len), dtype=np.int32)
+        lens = np.empty(idx.size, dtype=np.int32)
+        rc = lib().n2vo_walks_subset(*args, _p(idx, ctypes.c_int64), idx.size,
+                                     _p(Y, ctypes.c_int32), _p(lens, ctypes.c_int32))
+    if rc != OK:
+        raise OracleError(rc)
+    return Y, lens
+
+
+def walks_threaded(offsets, dst, weights, starts, walks_per_start, walk_len, kind, p=1.0, q=1.0,
+                   seed=0, walk_id_base=0, rows=None, threads=1):
+    """Same as walks(), with disjoint slices of `rows` handed to `threads` OS threads.
+
+    ctypes releases the GIL during each call, so the slices run concurrently;
+    the arithmetic is still the single-threaded C routine per slice."""
+    if rows is None:
+        rows = np.arange(len(starts) * walks_per_start, dtype=np.int64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    threads = max(1, min(int(threads), rows.size or 1))
+    parts = np.array_split(rows, threads)
+    out = [None] * threads
+
+    def run(i):
+        out[i] = walks(offsets, dst, weights, starts, walks_per_start, walk_len, kind, p, q, seed,
+                       walk_id_base, parts[i])
+
+    ts = [threading.Thread(target=run, args=(i,)) for i in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    Y = np.concatenate([o[0] for o in out]) if out else np.empty((0, walk_len), np.int32)
+    lens = np.concatenate([o[1] for o in out]) if out else np.empty(0, np.int32)
+    return Y, lens

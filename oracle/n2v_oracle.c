@@ -1,0 +1,227 @@
+/*
+ * Plain single-threaded CPU oracle for exact DeepWalk / node2vec walks.
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the GPU library.  See n2v_oracle.h
+ * for what each function computes and which passage of the paper it follows.
+ */
+#include "n2v_oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+
+/* ------------------------------------------------------------------------ */
+/* Q16 fixed point for the search-bias constants 1/p and 1/q (Eq. 1).        */
+/* ------------------------------------------------------------------------ */
+int n2vo_q16(double x, uint32_t* out) {
+  if (!(x > 0.0) || !isfinite(x)) return N2VO_ERR_INVALID_ARG;
+  double r = nearbyint(65536.0 / x); /* default rounding: to nearest, ties to even */
+  if (!(r >= 1.0) || !(r <= 4294967295.0)) return N2VO_ERR_INVALID_ARG;
+  *out = (uint32_t)r;
+  return N2VO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, as defined by Salmon et al. (SC'11): ten rounds of         */
+/*   (x0,x1,x2,x3) -> (hi(M1*x2) ^ x1 ^ k0, lo(M1*x2), hi(M0*x0) ^ x3 ^ k1,   */
+/*                     lo(M0*x0))                                            */
+/* with the key bumped by the Weyl constants between rounds.                 */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void n2vo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += PHILOX_W0;
+      k1 += PHILOX_W1;
+    }
+    uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+uint64_t n2vo_draw64(uint64_t seed, uint32_t step, uint64_t wid) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t ctr[4] = {step, (uint32_t)wid, (uint32_t)(wid >> 32), 0u};
+  uint32_t out[4];
+  n2vo_philox4x32_10(ctr, key, out);
+  return (uint64_t)out[0] | ((uint64_t)out[1] << 32);
+}
+
+/* Step 3 of the on-the-fly sampler: a uniform value in [0, total). */
+uint64_t n2vo_scale(uint64_t r64, uint64_t total) {
+  unsigned __int128 prod = (unsigned __int128)r64 * (unsigned __int128)total;
+  return (uint64_t)(prod >> 64);
+}
+
+/* ------------------------------------------------------------------------ */
+/* CSR checks and statistics (Methods, "Succinct data structures": the     */
+/* neighbours of a node form a sorted set).                                  */
+/* ------------------------------------------------------------------------ */
+int n2vo_validate(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m) {
+  if (n < 0) return N2VO_ERR_INVALID_ARG;
+  if (O[0] != 0) return N2VO_ERR_UNSORTED;
+  if (O[n] != m) return N2VO_ERR_UNSORTED;
+  for (int64_t v = 0; v < n; ++v) {
+    if (O[v + 1] < O[v]) return N2VO_ERR_UNSORTED;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    for (uint64_t e = O[v]; e < O[v + 1]; ++e) {
+      if (D[e] < 0 || (int64_t)D[e] >= n) return N2VO_ERR_UNSORTED;
+      if (e > O[v] && !(D[e - 1] < D[e])) return N2VO_ERR_UNSORTED;
+    }
+  }
+  return N2VO_OK;
+}
+
+void n2vo_stats(const uint64_t* O, int64_t n, const uint32_t* W,
+                uint64_t* max_deg, uint64_t* max_row_wsum) {
+  uint64_t md = 0, ms = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    uint64_t d = O[v + 1] - O[v];
+    uint64_t s = 0;
+    for (uint64_t e = O[v]; e < O[v + 1]; ++e) s += W ? (uint64_t)W[e] : 1u;
+    if (d > md) md = d;
+    if (s > ms) ms = s;
+  }
+  *max_deg = md;
+  *max_row_wsum = ms;
+}
+
+/* Is x a member of N(t)?  Binary search over the sorted row of t. */
+static int in_row(const uint64_t* O, const int32_t* D, int32_t t, int32_t x) {
+  uint64_t lo = O[t], hi = O[t + 1];
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (D[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < O[t + 1] && D[lo] == x;
+}
+
+/* Step 1 of the sampler: un-normalised transition weights pi_vx = alpha * w_vx
+ * (Eq. 1), alpha read with precedence return (x == t) > common neighbour
+ * (x in N(t), distance 1) > far (distance 2). */
+int64_t n2vo_step_weights(const uint64_t* O, const int32_t* D, const uint32_t* W,
+                          int32_t t, int32_t v, int second_order,
+                          uint32_t P16, uint32_t Q16, uint64_t* b) {
+  int64_t d = (int64_t)(O[v + 1] - O[v]);
+  for (int64_t j = 0; j < d; ++j) {
+    int32_t x = D[O[v] + j];
+    uint64_t w = W ? (uint64_t)W[O[v] + j] : 1u;
+    uint64_t a;
+    if (!second_order || t < 0) a = 1u;
+    else if (x == t) a = P16;
+    else if (in_row(O, D, t, x)) a = 65536u;
+    else a = Q16;
+    b[j] = w * a;
+  }
+  return d;
+}
+
+/* Step 4 of the sampler: first index whose cumulative sum exceeds T. */
+int64_t n2vo_select(const uint64_t* b, int64_t d, uint64_t T) {
+  uint64_t cum = 0;
+  for (int64_t j = 0; j < d; ++j) {
+    cum += b[j];
+    if (cum > T) return j;
+  }
+  return d;
+}
+
+/* One walk, slots Y[0..L): start, then up to L-1 steps, then -1 padding. */
+static int32_t one_walk(const uint64_t* O, int64_t n, const int32_t* D, const uint32_t* W,
+                        int32_t start, uint32_t L, int second_order,
+                        uint32_t P16, uint32_t Q16, uint64_t seed, uint64_t wid,
+                        uint64_t* b, int32_t* Y) {
+  for (uint32_t s = 0; s < L; ++s) Y[s] = -1;
+  if (start < 0 || (int64_t)start >= n) return 0;
+  Y[0] = start;
+  int32_t len = 1;
+  int32_t t = -1, v = start;
+  for (uint32_t s = 1; s < L; ++s) {
+    int64_t d = n2vo_step_weights(O, D, W, t, v, second_order, P16, Q16, b);
+    if (d == 0) break; /* dead end */
+    uint64_t total = 0;
+    for (int64_t j = 0; j < d; ++j) total += b[j];
+    if (total == 0) break; /* every candidate has weight zero */
+    uint64_t T = n2vo_scale(n2vo_draw64(seed, s, wid), total);
+    int64_t j = n2vo_select(b, d, T);
+    int32_t x = D[O[v] + j];
+    Y[s] = x;
+    len = (int32_t)s + 1;
+    t = v;
+    v = x;
+  }
+  return len;
+}
+
+int n2vo_walks_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+                      const uint32_t* W, const int32_t* S, int64_t ns,
+                      uint32_t reps, uint32_t L, int kind, double p, double q,
+                      uint64_t seed, uint64_t walk_id_base,
+                      const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens) {
+  if (n < 0 || ns < 0 || nw < 0 || L == 0 || reps == 0) return N2VO_ERR_INVALID_ARG;
+  for (int64_t k = 0; k < nw; ++k)
+    if (widx[k] < 0 || widx[k] >= ns * (int64_t)reps) return N2VO_ERR_INVALID_ARG;
+  if (kind != N2VO_FIRST_ORDER && kind != N2VO_NODE2VEC) return N2VO_ERR_INVALID_ARG;
+  uint32_t P16 = 65536u, Q16 = 65536u;
+  if (kind == N2VO_NODE2VEC) {
+    if (n2vo_q16(p, &P16) != N2VO_OK) return N2VO_ERR_INVALID_ARG;
+    if (n2vo_q16(q, &Q16) != N2VO_OK) return N2VO_ERR_INVALID_ARG;
+  }
+  /* Exactness precondition: every cumulative sum fits in 64 bits. */
+  uint64_t amax = 1u;
+  if (kind == N2VO_NODE2VEC) {
+    amax = 65536u;
+    if (P16 > amax) amax = P16;
+    if (Q16 > amax) amax = Q16;
+  }
+  uint64_t max_deg = 0, max_sum = 0;
+  n2vo_stats(O, n, W, &max_deg, &max_sum);
+  if ((unsigned __int128)max_sum * amax > (unsigned __int128)UINT64_MAX) return N2VO_ERR_OVERFLOW;
+
+  uint64_t* b = (uint64_t*)0;
+  if (max_deg > 0) {
+    b = (uint64_t*)malloc(sizeof(uint64_t) * max_deg);
+    if (!b) return N2VO_ERR_INVALID_ARG;
+  }
+  (void)m;
+  for (int64_t k = 0; k < nw; ++k) {
+    int64_t w = widx[k];
+    int32_t start = S[w % ns];
+    int32_t len = one_walk(O, n, D, W, start, L, kind == N2VO_NODE2VEC, P16, Q16, seed,
+                           walk_id_base + (uint64_t)w, b, Y + (size_t)k * L);
+    if (lens) lens[k] = len;
+  }
+  free(b);
+  return N2VO_OK;
+}
+
+int n2vo_walks(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+               const uint32_t* W, const int32_t* S, int64_t ns,
+               uint32_t reps, uint32_t L, int kind, double p, double q,
+               uint64_t seed, uint64_t walk_id_base, int32_t* Y, int32_t* lens) {
+  if (ns < 0 || reps == 0) return N2VO_ERR_INVALID_ARG;
+  int64_t nw = ns * (int64_t)reps;
+  int64_t* widx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nw > 0 ? nw : 1));
+  if (!widx) return N2VO_ERR_INVALID_ARG;
+  for (int64_t w = 0; w < nw; ++w) widx[w] = w;
+  int rc = n2vo_walks_subset(O, n, D, m, W, S, ns, reps, L, kind, p, q, seed, walk_id_base,
+                             widx, nw, Y, lens);
+  free(widx);
+  return rc;
+}

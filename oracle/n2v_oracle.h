@@ -1,0 +1,100 @@
+/*
+ * Plain single-threaded CPU oracle for exact first-order (DeepWalk) and
+ * second-order (node2vec) random-walk generation over a sorted CSR graph.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously correct
+ * definition the GPU path is checked against.  Only the test suite, the
+ * package smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no source with the GPU library.
+ *
+ * What it computes follows the paper's Methods, "First and second-order
+ * RW-based embedding methods":
+ *   - transition weight pi_vx = alpha_pq(t,x) * w_vx          (Eq. 1)
+ *   - alpha = 1/p if x == t, 1 if x in N(t), 1/q otherwise   (Eq. 1-3 and the
+ *     set-difference / return-bias reformulations that follow them)
+ *   - sampling on the fly: biased weights, cumulative sum, a uniform value in
+ *     [0, total), first index whose cumulative sum exceeds it   ("Efficient
+ *     sampling for Node2Vec RWs", steps 1-4)
+ * with 1/p and 1/q represented as Q16 fixed point so that the whole walk is
+ * exact integer arithmetic, and the uniform value taken from Philox4x32-10
+ * (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3",
+ * SC'11) keyed by (seed) with counter (step, walk id).
+ *
+ * Parity with the paper: pinned by closed-form transition probabilities,
+ * exact rational tables, brute-force walk enumeration and chi-square tests
+ * (tests/test_oracle_*.py).  Which particular walk a seed produces is fixed by
+ * this definition, not by the paper.
+ */
+#ifndef N2V_ORACLE_H
+#define N2V_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  N2VO_OK = 0,
+  N2VO_ERR_INVALID_ARG = -1,
+  N2VO_ERR_UNSORTED = -2,
+  N2VO_ERR_OVERFLOW = -3
+};
+
+enum { N2VO_FIRST_ORDER = 0, N2VO_NODE2VEC = 1 };
+
+/* 65536/x rounded to nearest, ties to even, in IEEE double; the result must
+ * lie in [1, 2^32-1].  Returns N2VO_OK or N2VO_ERR_INVALID_ARG. */
+int n2vo_q16(double x, uint32_t* out);
+
+/* Philox4x32 with 10 rounds: ctr[4], key[2] -> out[4]. */
+void n2vo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The 64-bit uniform draw of step s of walk `wid`:
+ * key = (seed lo, seed hi), counter = (s, wid lo, wid hi, 0),
+ * r64 = out0 | out1 << 32. */
+uint64_t n2vo_draw64(uint64_t seed, uint32_t step, uint64_t wid);
+
+/* floor(r64 * total / 2^64): a uniform value in [0, total). */
+uint64_t n2vo_scale(uint64_t r64, uint64_t total);
+
+/* CSR validity: O[0]==0, O non-decreasing, O[n]==m, every row strictly
+ * increasing, every destination in [0,n).  Returns N2VO_OK or
+ * N2VO_ERR_UNSORTED. */
+int n2vo_validate(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m);
+
+/* Max degree and max row weight sum (weights NULL = all ones). */
+void n2vo_stats(const uint64_t* O, int64_t n, const uint32_t* W,
+                uint64_t* max_deg, uint64_t* max_row_wsum);
+
+/* Biased weights of every candidate x in N(v) for one step from v whose
+ * previous node is t (t < 0: no previous node, first step).
+ * second_order == 0 or t < 0: a = 1; else a = P16 if x == t, 65536 if
+ * x in N(t), Q16 otherwise.  b[j] = w_j * a_j.  Returns d_v. */
+int64_t n2vo_step_weights(const uint64_t* O, const int32_t* D, const uint32_t* W,
+                          int32_t t, int32_t v, int second_order,
+                          uint32_t P16, uint32_t Q16, uint64_t* b);
+
+/* First j with b[0]+...+b[j] > T (plain linear scan); d if none. */
+int64_t n2vo_select(const uint64_t* b, int64_t d, uint64_t T);
+
+/* Generate the walks whose row indices are listed in widx[0..nw).
+ * Row w uses start S[w mod ns] and walk id walk_id_base + w.
+ * Y is [nw][L] (row k belongs to walk widx[k]); lens is [nw] or NULL.
+ * kind: N2VO_FIRST_ORDER or N2VO_NODE2VEC (p, q ignored for first order).
+ * Returns N2VO_OK, N2VO_ERR_INVALID_ARG or N2VO_ERR_OVERFLOW. */
+int n2vo_walks_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+                      const uint32_t* W, const int32_t* S, int64_t ns,
+                      uint32_t reps, uint32_t L, int kind, double p, double q,
+                      uint64_t seed, uint64_t walk_id_base,
+                      const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens);
+
+/* All reps*ns walks, row w = rep*ns + i. */
+int n2vo_walks(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+               const uint32_t* W, const int32_t* S, int64_t ns,
+               uint32_t reps, uint32_t L, int kind, double p, double q,
+               uint64_t seed, uint64_t walk_id_base, int32_t* Y, int32_t* lens);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
