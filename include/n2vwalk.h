@@ -1,0 +1,206 @@
+/*
+ * n2vwalk: exact first-order (DeepWalk) and second-order (node2vec) random-walk
+ * generation over a sorted CSR graph on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the one defined in the paper's Methods, "First and
+ * second-order RW-based embedding methods":
+ *   - a first-order step from v picks x in N(v) with probability w_vx / sum_x w_vx;
+ *   - a node2vec step from v, arrived at from t, picks x with probability
+ *     proportional to pi_vx = alpha_pq(t,x) * w_vx, where alpha is 1/p if x == t,
+ *     1 if x is a neighbour of t, and 1/q otherwise (Eq. 1, and its split into
+ *     the return and in-out biases, Eq. 2-3);
+ *   - sampling is done on the fly (section "Efficient sampling for Node2Vec
+ *     RWs"): biased weights, their cumulative sum, a uniform value in
+ *     [0, total), and the first index whose cumulative sum exceeds it.
+ *
+ * Exact integer arithmetic: weights are uint32, 1/p and 1/q are Q16 fixed
+ * point (P16 = round-half-even(65536/p), Q16 likewise, C16 = 65536), running
+ * sums are uint64, and the uniform value is floor(r64 * total / 2^64) with
+ * r64 = out0 | out1 << 32 of Philox4x32-10 (Salmon et al., SC'11) under key
+ * (seed lo, seed hi) and counter (step, walk id lo, walk id hi, 0).  The first
+ * step of a node2vec walk, which has no previous node, is a first-order step.
+ * Every walk is therefore a pure function of (graph, kind, start, walk length,
+ * P16, Q16, seed, walk id), independent of stream, tuning and batch company.
+ *
+ * Conventions for every function:
+ *   - returns an int32 status (N2V_OK or a negative N2V_ERR_*); never throws;
+ *     n2v_last_error() gives a message for the calling thread's last failure;
+ *   - "device pointer" means memory the GPU can read/write (hipMalloc, torch
+ *     CUDA tensors); "host pointer" means ordinary CPU memory;
+ *   - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *
+ * Walk output layout: walks is int32[n_walks][walk_len], row-major, with
+ * n_walks = walks_per_start * n_starts and row w = rep * n_starts + i using
+ * start starts[i] and walk id walk_id_base + w.  Slot 0 holds the start; a walk
+ * that reaches a node with no out-edge (or whose candidates all have weight
+ * zero) stops there; unused slots hold -1.  lens[w] = number of slots written
+ * (walk_len for a full walk, 0 for a start outside [0, n_nodes)).
+ */
+#ifndef N2VWALK_H
+#define N2VWALK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  N2V_OK = 0,
+  N2V_PENDING = 1,          /* n2v_request_poll: not finished yet (not an error) */
+  N2V_ERR_INVALID_ARG = -1, /* NULL pointer, zero size where one is needed, walk_len == 0,
+                               walks_per_start == 0, p or q not finite and > 0, or their
+                               Q16 value outside [1, 2^32-1] */
+  N2V_ERR_UNSORTED = -2,    /* offsets[0] != 0, offsets not monotone, offsets[n] != n_entries,
+                               a row not strictly increasing, or a destination outside [0,n) */
+  N2V_ERR_OVERFLOW = -3,    /* max row weight sum * max(P16, 65536, Q16) >= 2^64 */
+  N2V_ERR_NOMEM = -4,       /* device or host allocation failed */
+  N2V_ERR_HIP = -5,         /* a HIP runtime call failed (message in n2v_last_error) */
+  N2V_ERR_BAD_HANDLE = -6,  /* unknown or released handle */
+  N2V_ERR_REJECTED = -7     /* request can never fit the server's memory budget */
+};
+
+enum { N2V_FIRST_ORDER = 0, N2V_NODE2VEC = 1 };
+
+typedef uint64_t n2v_graph;   /* opaque, 0 = invalid */
+typedef uint64_t n2v_server;  /* opaque, 0 = invalid */
+typedef uint64_t n2v_request; /* opaque, 0 = invalid */
+
+typedef struct {
+  uint64_t n_nodes;
+  uint64_t n_entries;
+  uint64_t max_degree;
+  uint64_t max_row_wsum;   /* max over rows of the sum of weights (degree if unweighted) */
+  uint64_t sum_deg_sq;     /* sum over nodes of degree^2 (stationary mean degree = this / n_entries) */
+  uint32_t weighted;       /* 1 if weights were given */
+  uint32_t prefix_bytes;   /* 0 (unweighted), 4 or 8: width of the per-row weight prefix */
+  uint64_t device_bytes;   /* library-owned device memory held by this graph */
+} n2v_graph_info_t;
+
+/* Launch tuning.  Zero fields mean "automatic".  Tuning never changes a walk:
+ * every setting produces bit-identical output. */
+typedef struct {
+  uint32_t lanes_per_walker; /* generic node2vec path: 4, 8, 16, 32 or 64 lanes per walker */
+  uint32_t hub_threshold;    /* degree above which a step uses the whole-wavefront hub path;
+                                UINT32_MAX disables it */
+  uint32_t lds_tile;         /* entries of the previous node's row kept in LDS per walker */
+  uint32_t flags;            /* N2V_TUNE_* bits */
+} n2v_tuning_t;
+
+enum {
+  N2V_TUNE_GENERIC_ONLY = 1u,  /* route every step through the generic node2vec path
+                                  (no first-order / q == 1 specialisations) */
+  N2V_TUNE_NO_ASYMMETRIC = 2u  /* hub path: always stream the row, never probe N(t) into N(v) */
+};
+
+/* ---------------------------------------------------------------------------
+ * Graph residency (once per graph).
+ *
+ * d_offsets: device uint64[n_nodes+1]; d_dst: device int32[n_entries]; each row
+ * d_dst[offsets[v] .. offsets[v+1]) strictly increasing (the sorted neighbour
+ * set of the paper's CSR store, Methods "Succinct data structures").
+ * d_weights: device uint32[n_entries], or NULL for an unweighted graph
+ * (every weight 1).  flags must be 0.
+ * The three arrays are BORROWED: the caller keeps them alive and unchanged
+ * until n2v_graph_release.  Derived arrays (per-row inclusive weight prefix,
+ * statistics) are owned by the library.
+ * Synchronous: validates on the device, builds the derived arrays on
+ * hip_stream and waits for it.  Errors: INVALID_ARG, UNSORTED, NOMEM, HIP.
+ * ------------------------------------------------------------------------- */
+int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst,
+                     uint64_t n_entries, const uint32_t* d_weights, uint32_t flags,
+                     void* hip_stream, n2v_graph* out);
+int n2v_graph_info(n2v_graph g, n2v_graph_info_t* out);
+/* Frees the library-owned arrays.  The caller must make sure no walk on g is
+ * still running (synchronise the streams first). */
+int n2v_graph_release(n2v_graph g);
+
+/* ---------------------------------------------------------------------------
+ * Plain walk generation (one launch per call).
+ *
+ * d_starts: device int32[n_starts]; d_walks: device int32[walks_per_start *
+ * n_starts][walk_len]; d_lens: device int32[walks_per_start * n_starts] or NULL.
+ * All caller-owned.  Arguments are validated synchronously, then the work is
+ * enqueued on hip_stream; the outputs are valid once the stream has been
+ * synchronised.  A start outside [0, n_nodes) yields a row of -1 with length 0
+ * (not an error).  n_starts == 0 is a no-op.  Reentrant across streams.
+ * Errors: INVALID_ARG, BAD_HANDLE, OVERFLOW (node2vec), HIP.
+ * ------------------------------------------------------------------------- */
+int n2v_walks_first_order(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
+                          uint32_t walks_per_start, uint32_t walk_len, uint64_t seed,
+                          uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens,
+                          void* hip_stream);
+int n2v_walks_node2vec(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
+                       uint32_t walks_per_start, uint32_t walk_len, double p, double q,
+                       uint64_t seed, uint64_t walk_id_base, int32_t* d_walks,
+                       int32_t* d_lens, void* hip_stream);
+
+/* Process-wide tuning override (NULL restores automatic tuning).  Used to
+ * show that every tuning point yields identical walks. */
+int n2v_set_tuning(const n2v_tuning_t* tuning);
+
+/* ---------------------------------------------------------------------------
+ * Batched generation: many requests (different graphs, kinds, lengths, p, q,
+ * seeds) in ONE persistent launch fed by a device work queue of walk chunks,
+ * longest estimated work first.  Each request's output is bit-identical to the
+ * plain call with the same arguments.  reqs is a host array; the pointers
+ * inside are device pointers as in the plain calls.  Enqueued on hip_stream;
+ * the host array may be reused as soon as the call returns.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  n2v_graph graph;
+  uint32_t kind;            /* N2V_FIRST_ORDER or N2V_NODE2VEC */
+  uint32_t walks_per_start;
+  uint32_t walk_len;
+  uint32_t reserved;
+  double p, q;              /* ignored for first order */
+  uint64_t seed;
+  uint64_t walk_id_base;
+  const int32_t* d_starts;
+  uint64_t n_starts;
+  int32_t* d_walks;
+  int32_t* d_lens;          /* may be NULL */
+} n2v_request_desc_t;
+
+int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: resident graphs, requests admitted by memory footprint, continuous
+ * batching (requests that arrive while others run are started as slots and
+ * memory free up; their walks overlap on the device).  Thread-safe.
+ *
+ * n2v_server_create: hbm_budget_bytes caps the device memory the server holds
+ * for request inputs and results; max_slots caps requests in flight.
+ * n2v_server_add_graph: makes g servable (g stays owned by the caller and must
+ * outlive the server).
+ * n2v_request_submit: desc as above but d_starts is a HOST pointer (copied at
+ * submit) and d_walks / d_lens are ignored (the server allocates the results).
+ * arrival_ns is the caller's timestamp (CLOCK_MONOTONIC) for latency
+ * accounting.  Errors: REJECTED if the request alone exceeds the budget.
+ * n2v_request_poll: N2V_PENDING until done, then N2V_OK and *out filled;
+ * results stay valid until n2v_request_release.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const int32_t* d_walks;   /* device int32[n_walks][walk_len], server-owned */
+  const int32_t* d_lens;    /* device int32[n_walks], server-owned */
+  uint64_t n_walks;
+  uint64_t steps;           /* sum over walks of (len - 1), transitions taken */
+  uint64_t t_arrival_ns, t_admit_ns, t_start_ns, t_done_ns; /* CLOCK_MONOTONIC */
+} n2v_result_t;
+
+int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, void* reserved,
+                      n2v_server* out);
+int n2v_server_add_graph(n2v_server s, n2v_graph g);
+int n2v_request_submit(n2v_server s, const n2v_request_desc_t* desc, uint64_t arrival_ns,
+                       n2v_request* out);
+int n2v_request_poll(n2v_server s, n2v_request r, n2v_result_t* out);
+int n2v_request_release(n2v_server s, n2v_request r);
+int n2v_server_destroy(n2v_server s);
+
+/* Thread-local message describing the calling thread's last error ("" if none). */
+const char* n2v_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* N2VWALK_H */

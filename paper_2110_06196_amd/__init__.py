@@ -1,0 +1,250 @@
+"""Exact DeepWalk / node2vec walk generation on AMD Instinct MI355X.
+
+Thin ctypes binding over the C ABI in ``include/n2vwalk.h`` (library
+``libn2vwalk.so``, built by ``paper_2110_06196_amd.build``).  The functions
+keep the C names; they take torch tensors for device memory and torch streams,
+marshal pointers and sizes, and raise ``N2VError`` on a non-zero status.
+Every step of the walk runs in the library's HIP kernels: there is no CPU or
+PyTorch fallback, and importing this module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # loaded first so the library binds to the same HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libn2vwalk.so")
+
+N2V_OK, N2V_PENDING = 0, 1
+N2V_ERR_INVALID_ARG, N2V_ERR_UNSORTED, N2V_ERR_OVERFLOW = -1, -2, -3
+N2V_ERR_NOMEM, N2V_ERR_HIP, N2V_ERR_BAD_HANDLE, N2V_ERR_REJECTED = -4, -5, -6, -7
+N2V_FIRST_ORDER, N2V_NODE2VEC = 0, 1
+N2V_TUNE_GENERIC_ONLY, N2V_TUNE_NO_ASYMMETRIC = 1, 2
+
+_STATUS = {
+    0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "UNSORTED", -3: "OVERFLOW", -4: "NOMEM",
+    -5: "HIP", -6: "BAD_HANDLE", -7: "REJECTED",
+}
+
+
+class N2VError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_uint64), ("n_entries", ctypes.c_uint64),
+                ("max_degree", ctypes.c_uint64), ("max_row_wsum", ctypes.c_uint64),
+                ("sum_deg_sq", ctypes.c_uint64), ("weighted", ctypes.c_uint32),
+                ("prefix_bytes", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("lanes_per_walker", ctypes.c_uint32), ("hub_threshold", ctypes.c_uint32),
+                ("lds_tile", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class RequestDesc(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_uint64), ("kind", ctypes.c_uint32),
+                ("walks_per_start", ctypes.c_uint32), ("walk_len", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("p", ctypes.c_double), ("q", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("walk_id_base", ctypes.c_uint64),
+                ("d_starts", ctypes.c_void_p), ("n_starts", ctypes.c_uint64),
+                ("d_walks", ctypes.c_void_p), ("d_lens", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("d_walks", ctypes.c_void_p), ("d_lens", ctypes.c_void_p),
+                ("n_walks", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("t_arrival_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+# Every exported symbol with its ctypes signature (also checked by the tests).
+_U64, _U32, _I32, _VP, _D = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_double
+SIGNATURES = {
+    "n2v_graph_upload": [_VP, _U64, _VP, _U64, _VP, _U32, _VP, ctypes.POINTER(_U64)],
+    "n2v_graph_info": [_U64, ctypes.POINTER(GraphInfo)],
+    "n2v_graph_release": [_U64],
+    "n2v_walks_first_order": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP, _VP],
+    "n2v_walks_node2vec": [_U64, _VP, _U64, _U32, _U32, _D, _D, _U64, _U64, _VP, _VP, _VP],
+    "n2v_set_tuning": [ctypes.POINTER(Tuning)],
+    "n2v_walks_batched": [ctypes.POINTER(RequestDesc), _U32, _VP],
+    "n2v_server_create": [_U64, _U32, _VP, ctypes.POINTER(_U64)],
+    "n2v_server_add_graph": [_U64, _U64],
+    "n2v_request_submit": [_U64, ctypes.POINTER(RequestDesc), _U64, ctypes.POINTER(_U64)],
+    "n2v_request_poll": [_U64, _U64, ctypes.POINTER(Result)],
+    "n2v_request_release": [_U64, _U64],
+    "n2v_server_destroy": [_U64],
+    "n2v_last_error": [],
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libn2vwalk.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -m paper_2110_06196_amd.build` (HIP for gfx950)")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, args in SIGNATURES.items():
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = ctypes.c_char_p if name == "n2v_last_error" else ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise N2VError(rc, lib().n2v_last_error().decode(errors="replace"))
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise N2VError(N2V_ERR_INVALID_ARG, f"{name} must be a contiguous CUDA {dtype} tensor")
+    return t
+
+
+# ---------------------------------------------------------------------------
+# Graphs
+# ---------------------------------------------------------------------------
+def n2v_graph_upload(offsets, dst, weights=None, stream=None) -> int:
+    """Register a CSR graph held in device tensors (uint64 / int64 offsets,
+    int32 destinations, optional int32/uint32 weights viewed as uint32).
+    The tensors are borrowed: keep them alive until n2v_graph_release."""
+    if offsets.dtype == torch.int64:
+        offsets = offsets.view(torch.uint64) if hasattr(torch, "uint64") else offsets
+    _dev(dst, torch.int32, "dst")
+    if weights is not None and weights.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        raise N2VError(N2V_ERR_INVALID_ARG, "weights must be uint32 (or int32 bit pattern)")
+    h = ctypes.c_uint64(0)
+    _check(lib().n2v_graph_upload(_ptr(offsets), offsets.numel() - 1, _ptr(dst), dst.numel(),
+                                  _ptr(weights), 0, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def n2v_graph_info(g: int) -> dict:
+    info = GraphInfo()
+    _check(lib().n2v_graph_info(g, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in GraphInfo._fields_}
+
+
+def n2v_graph_release(g: int) -> None:
+    _check(lib().n2v_graph_release(g))
+
+
+def n2v_set_tuning(lanes_per_walker=0, hub_threshold=0, lds_tile=0, flags=0, reset=False) -> None:
+    if reset:
+        _check(lib().n2v_set_tuning(None))
+        return
+    t = Tuning(lanes_per_walker, hub_threshold, lds_tile, flags)
+    _check(lib().n2v_set_tuning(ctypes.byref(t)))
+
+
+# ---------------------------------------------------------------------------
+# Plain walks
+# ---------------------------------------------------------------------------
+def _alloc_out(starts, walks_per_start, walk_len, walks, lens):
+    nw = starts.numel() * walks_per_start
+    if walks is None:
+        walks = torch.empty((nw, walk_len), dtype=torch.int32, device=starts.device)
+    if lens is None:
+        lens = torch.empty(nw, dtype=torch.int32, device=starts.device)
+    _dev(walks, torch.int32, "walks")
+    _dev(lens, torch.int32, "lens")
+    if walks.numel() != nw * walk_len or lens.numel() != nw:
+        raise N2VError(N2V_ERR_INVALID_ARG, "walks / lens have the wrong size")
+    return walks, lens
+
+
+def n2v_walks_first_order(g: int, starts, walks_per_start: int, walk_len: int, seed: int,
+                          walk_id_base: int = 0, walks=None, lens=None, stream=None):
+    """Enqueue first-order walks; returns (walks int32[n][walk_len], lens int32[n])."""
+    _dev(starts, torch.int32, "starts")
+    walks, lens = _alloc_out(starts, walks_per_start, walk_len, walks, lens)
+    _check(lib().n2v_walks_first_order(g, _ptr(starts), starts.numel(), walks_per_start, walk_len,
+                                       seed, walk_id_base, _ptr(walks), _ptr(lens), _stream(stream)))
+    return walks, lens
+
+
+def n2v_walks_node2vec(g: int, starts, walks_per_start: int, walk_len: int, p: float, q: float,
+                       seed: int, walk_id_base: int = 0, walks=None, lens=None, stream=None):
+    """Enqueue node2vec walks; returns (walks int32[n][walk_len], lens int32[n])."""
+    _dev(starts, torch.int32, "starts")
+    walks, lens = _alloc_out(starts, walks_per_start, walk_len, walks, lens)
+    _check(lib().n2v_walks_node2vec(g, _ptr(starts), starts.numel(), walks_per_start, walk_len,
+                                    float(p), float(q), seed, walk_id_base, _ptr(walks), _ptr(lens),
+                                    _stream(stream)))
+    return walks, lens
+
+
+def make_request(graph: int, kind: int, starts, walks_per_start: int, walk_len: int, p=1.0, q=1.0,
+                 seed=0, walk_id_base=0, walks=None, lens=None) -> RequestDesc:
+    return RequestDesc(graph, kind, walks_per_start, walk_len, 0, float(p), float(q), seed,
+                       walk_id_base, starts.data_ptr() if starts is not None else None,
+                       starts.numel() if starts is not None else 0,
+                       walks.data_ptr() if walks is not None else None,
+                       lens.data_ptr() if lens is not None else None)
+
+
+def n2v_walks_batched(reqs, stream=None) -> None:
+    """reqs: list of RequestDesc (device pointers inside); one launch."""
+    arr = (RequestDesc * len(reqs))(*reqs)
+    _check(lib().n2v_walks_batched(arr, len(reqs), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+def n2v_server_create(hbm_budget_bytes: int, max_slots: int) -> int:
+    h = ctypes.c_uint64(0)
+    _check(lib().n2v_server_create(hbm_budget_bytes, max_slots, None, ctypes.byref(h)))
+    return h.value
+
+
+def n2v_server_add_graph(s: int, g: int) -> None:
+    _check(lib().n2v_server_add_graph(s, g))
+
+
+def n2v_request_submit(s: int, desc: RequestDesc, arrival_ns: int) -> int:
+    h = ctypes.c_uint64(0)
+    _check(lib().n2v_request_submit(s, ctypes.byref(desc), arrival_ns, ctypes.byref(h)))
+    return h.value
+
+
+def n2v_request_poll(s: int, r: int):
+    """Returns None while pending, else a Result."""
+    res = Result()
+    rc = _check(lib().n2v_request_poll(s, r, ctypes.byref(res)))
+    return None if rc == N2V_PENDING else res
+
+
+def n2v_request_release(s: int, r: int) -> None:
+    _check(lib().n2v_request_release(s, r))
+
+
+def n2v_server_destroy(s: int) -> None:
+    _check(lib().n2v_server_destroy(s))

@@ -1,0 +1,316 @@
+// C ABI of the walk library: argument validation, graph registry, variant
+// dispatch and tuning.  Declarations and semantics: include/n2vwalk.h.
+#include "n2vwalk.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "n2v_internal.hpp"
+#include "n2v_runtime.hpp"
+
+namespace n2v {
+
+thread_local std::string t_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(N2V_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+
+std::mutex g_mu;
+std::unordered_map<uint64_t, GraphRec*> g_graphs;
+uint64_t g_next_graph = 1;
+bool g_tune_set = false;
+n2v_tuning_t g_tune{};
+
+std::mutex g_dev_mu;
+std::unordered_map<int, DevInfo> g_devs;
+
+}  // namespace
+
+int q16_of(double x, uint32_t* out) {
+  if (!(x > 0.0) || !std::isfinite(x)) return N2V_ERR_INVALID_ARG;
+  const double r = std::nearbyint(65536.0 / x);  // round to nearest, ties to even
+  if (!(r >= 1.0) || !(r <= 4294967295.0)) return N2V_ERR_INVALID_ARG;
+  *out = (uint32_t)r;
+  return N2V_OK;
+}
+
+int current_devinfo(DevInfo* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_devs.find(dev);
+  if (it == g_devs.end()) {
+    DevInfo di;
+    di.device = dev;
+    e = hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    int lds = 0;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    di.lds_per_block_max = (size_t)lds;
+    it = g_devs.emplace(dev, di).first;
+  }
+  *out = it->second;
+  return N2V_OK;
+}
+
+GraphRec* find_graph(n2v_graph g) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_graphs.find(g);
+  return it == g_graphs.end() ? nullptr : it->second;
+}
+
+// Launch configuration for one request on one graph.  The automatic choice
+// follows the graph's stationary mean degree sum(d^2)/sum(d): the expected
+// number of candidates per step of a long walk.
+LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
+  LaunchCfg c;
+  const double ed = gr.n_entries ? (double)gr.sum_deg_sq / (double)gr.n_entries : 0.0;
+  c.lanes_per_walker = ed > 256 ? 64 : (ed > 48 ? 32 : 16);
+  c.lds_tile = c.lanes_per_walker == 64 ? 1024 : (c.lanes_per_walker == 32 ? 512 : 256);
+  c.hub_threshold = 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_tune_set) {
+    if (g_tune.lanes_per_walker) c.lanes_per_walker = (int)g_tune.lanes_per_walker;
+    if (g_tune.lds_tile) c.lds_tile = (int)g_tune.lds_tile;
+    if (g_tune.hub_threshold) c.hub_threshold = g_tune.hub_threshold;
+    c.no_asym = (g_tune.flags & N2V_TUNE_NO_ASYMMETRIC) != 0;
+  }
+  // keep the per-block LDS inside the hardware limit
+  const size_t gpb = 256 / (size_t)c.lanes_per_walker;
+  while (c.lds_tile > 1 && gpb * 2 * (size_t)c.lds_tile * 4 > di.lds_per_block_max) c.lds_tile /= 2;
+  return c;
+}
+
+bool generic_only() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tune_set && (g_tune.flags & N2V_TUNE_GENERIC_ONLY);
+}
+
+// Validate a walk request and fill the kernel arguments.
+int prepare_request(const GraphRec& gr, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
+                    uint32_t walks_per_start, uint32_t walk_len, double p, double q, uint64_t seed,
+                    uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens, WalkArgs* a,
+                    Path* path) {
+  if (walk_len == 0) return fail(N2V_ERR_INVALID_ARG, "walk_len must be >= 1");
+  if (walks_per_start == 0) return fail(N2V_ERR_INVALID_ARG, "walks_per_start must be >= 1");
+  if (kind != N2V_FIRST_ORDER && kind != N2V_NODE2VEC) return fail(N2V_ERR_INVALID_ARG, "bad kind");
+  if (n_starts > 0 && (!d_starts || !d_walks))
+    return fail(N2V_ERR_INVALID_ARG, "starts and walks must be non-NULL");
+  const unsigned __int128 nw = (unsigned __int128)n_starts * walks_per_start;
+  if (nw * walk_len >= ((unsigned __int128)1 << 62)) return fail(N2V_ERR_INVALID_ARG, "output too large");
+  uint32_t P16 = kC16Host, Q16 = kC16Host;
+  if (kind == N2V_NODE2VEC) {
+    if (q16_of(p, &P16) != N2V_OK) return fail(N2V_ERR_INVALID_ARG, "p=%g gives no Q16 value in [1, 2^32-1]", p);
+    if (q16_of(q, &Q16) != N2V_OK) return fail(N2V_ERR_INVALID_ARG, "q=%g gives no Q16 value in [1, 2^32-1]", q);
+    uint64_t amax = kC16Host;
+    if (P16 > amax) amax = P16;
+    if (Q16 > amax) amax = Q16;
+    if ((unsigned __int128)gr.max_row_wsum * amax > (unsigned __int128)UINT64_MAX)
+      return fail(N2V_ERR_OVERFLOW, "max row weight sum %llu * %llu does not fit in 64 bits",
+                  (unsigned long long)gr.max_row_wsum, (unsigned long long)amax);
+  }
+  a->g = gr.dev;
+  a->starts = d_starts;
+  a->ns = n_starts;
+  a->nwalks = (uint64_t)nw;
+  a->L = walk_len;
+  a->second_order = kind == N2V_NODE2VEC ? 1u : 0u;
+  a->P16 = P16;
+  a->Q16 = Q16;
+  a->seed = seed;
+  a->wid_base = walk_id_base;
+  a->Y = d_walks;
+  a->lens = d_lens;
+  // Variant dispatch (the paper's eight specialisations): first order and
+  // node2vec with p = q = 1 share the first-order kernels; node2vec with
+  // 1/q == 1 only re-weights the return edge; everything else is generic.
+  if (generic_only()) *path = Path::kGeneric;
+  else if (kind == N2V_FIRST_ORDER || (P16 == kC16Host && Q16 == kC16Host)) {
+    *path = Path::kFirstOrder;
+    a->second_order = 0;
+  } else if (Q16 == kC16Host) *path = Path::kReturnOnly;
+  else *path = Path::kGeneric;
+  return N2V_OK;
+}
+
+}  // namespace n2v
+
+using namespace n2v;
+
+extern "C" {
+
+const char* n2v_last_error(void) { return t_err.c_str(); }
+
+int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst,
+                     uint64_t n_entries, const uint32_t* d_weights, uint32_t flags,
+                     void* hip_stream, n2v_graph* out) {
+  if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
+  *out = 0;
+  if (!d_offsets) return fail(N2V_ERR_INVALID_ARG, "offsets is NULL");
+  if (n_entries > 0 && !d_dst) return fail(N2V_ERR_INVALID_ARG, "dst is NULL");
+  if (flags != 0) return fail(N2V_ERR_INVALID_ARG, "flags must be 0");
+  if (n_nodes > (uint64_t)INT32_MAX) return fail(N2V_ERR_INVALID_ARG, "node ids must fit in int32");
+  if (n_entries >= ((uint64_t)1 << 62)) return fail(N2V_ERR_INVALID_ARG, "too many entries");
+  DevInfo di;
+  int rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  uint64_t* d_stats = nullptr;
+  hipError_t e = hipMalloc(&d_stats, 4 * sizeof(uint64_t));
+  if (e != hipSuccess) return fail(N2V_ERR_NOMEM, "hipMalloc stats: %s", hipGetErrorString(e));
+  uint64_t h[4] = {0, 0, 0, 0};
+  e = hipMemsetAsync(d_stats, 0, 4 * sizeof(uint64_t), st);
+  if (e == hipSuccess) e = launch_validate_stats(d_offsets, (int64_t)n_nodes, d_dst, n_entries, d_weights, d_stats, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d_stats, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(d_stats);
+  if (e != hipSuccess) return hip_fail(e, "graph validation");
+  if (h[0]) {
+    return fail(N2V_ERR_UNSORTED, "invalid CSR:%s%s%s", (h[0] & kErrOffsets) ? " offsets" : "",
+                (h[0] & kErrOrder) ? " row-not-strictly-increasing" : "",
+                (h[0] & kErrRange) ? " destination-out-of-range" : "");
+  }
+  GraphRec* gr = new GraphRec();
+  gr->dev.O = d_offsets;
+  gr->dev.D = d_dst;
+  gr->dev.W = d_weights;
+  gr->dev.n = (int64_t)n_nodes;
+  gr->dev.m = n_entries;
+  gr->n_nodes = n_nodes;
+  gr->n_entries = n_entries;
+  gr->max_degree = h[1];
+  gr->max_row_wsum = h[2];
+  gr->sum_deg_sq = h[3];
+  gr->weighted = d_weights ? 1u : 0u;
+  gr->device = di.device;
+  if (d_weights && n_entries > 0) {
+    const uint32_t rb = gr->max_row_wsum <= 0xFFFFFFFFull ? 4u : 8u;
+    void* R = nullptr;
+    e = hipMalloc(&R, (size_t)n_entries * rb);
+    if (e != hipSuccess) {
+      delete gr;
+      return fail(N2V_ERR_NOMEM, "hipMalloc prefix (%llu bytes): %s",
+                  (unsigned long long)(n_entries * rb), hipGetErrorString(e));
+    }
+    e = launch_row_prefix(d_offsets, (int64_t)n_nodes, d_weights, R, rb, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      hipFree(R);
+      delete gr;
+      return hip_fail(e, "row prefix");
+    }
+    gr->dev.R = R;
+    gr->dev.r_bytes = rb;
+    gr->owned_bytes += (uint64_t)n_entries * rb;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    gr->handle = g_next_graph++;
+    g_graphs[gr->handle] = gr;
+  }
+  *out = gr->handle;
+  return N2V_OK;
+}
+
+int n2v_graph_info(n2v_graph g, n2v_graph_info_t* out) {
+  if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
+  GraphRec* gr = find_graph(g);
+  if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
+  out->n_nodes = gr->n_nodes;
+  out->n_entries = gr->n_entries;
+  out->max_degree = gr->max_degree;
+  out->max_row_wsum = gr->max_row_wsum;
+  out->sum_deg_sq = gr->sum_deg_sq;
+  out->weighted = gr->weighted;
+  out->prefix_bytes = gr->dev.r_bytes;
+  out->device_bytes = gr->owned_bytes;
+  return N2V_OK;
+}
+
+int n2v_graph_release(n2v_graph g) {
+  GraphRec* gr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find(g);
+    if (it == g_graphs.end()) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
+    gr = it->second;
+    g_graphs.erase(it);
+  }
+  if (gr->dev.R) hipFree(const_cast<void*>(gr->dev.R));
+  delete gr;
+  return N2V_OK;
+}
+
+int n2v_set_tuning(const n2v_tuning_t* tuning) {
+  if (tuning) {
+    const uint32_t g = tuning->lanes_per_walker;
+    if (g != 0 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
+      return fail(N2V_ERR_INVALID_ARG, "lanes_per_walker must be 4, 8, 16, 32 or 64");
+    if (tuning->lds_tile > (1u << 16)) return fail(N2V_ERR_INVALID_ARG, "lds_tile too large");
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tune_set = tuning != nullptr;
+  if (tuning) g_tune = *tuning;
+  return N2V_OK;
+}
+
+static int walks_common(n2v_graph g, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
+                        uint32_t walks_per_start, uint32_t walk_len, double p, double q,
+                        uint64_t seed, uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens,
+                        void* hip_stream) {
+  GraphRec* gr = find_graph(g);
+  if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
+  WalkArgs a;
+  Path path;
+  int rc = prepare_request(*gr, kind, d_starts, n_starts, walks_per_start, walk_len, p, q, seed,
+                           walk_id_base, d_walks, d_lens, &a, &path);
+  if (rc != N2V_OK) return rc;
+  if (a.nwalks == 0) return N2V_OK;
+  DevInfo di;
+  rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  LaunchCfg cfg = choose_cfg(*gr, di);
+  hipError_t e = launch_walks(a, path, cfg, di, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "walk launch");
+  return N2V_OK;
+}
+
+int n2v_walks_first_order(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
+                          uint32_t walks_per_start, uint32_t walk_len, uint64_t seed,
+                          uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens,
+                          void* hip_stream) {
+  return walks_common(g, N2V_FIRST_ORDER, d_starts, n_starts, walks_per_start, walk_len, 1.0, 1.0,
+                      seed, walk_id_base, d_walks, d_lens, hip_stream);
+}
+
+int n2v_walks_node2vec(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
+                       uint32_t walks_per_start, uint32_t walk_len, double p, double q,
+                       uint64_t seed, uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens,
+                       void* hip_stream) {
+  return walks_common(g, N2V_NODE2VEC, d_starts, n_starts, walks_per_start, walk_len, p, q, seed,
+                      walk_id_base, d_walks, d_lens, hip_stream);
+}
+
+}  // extern "C"

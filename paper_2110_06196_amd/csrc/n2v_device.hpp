@@ -1,0 +1,103 @@
+// Device-side building blocks shared by the walk and prep kernels (gfx950,
+// wave64).  Everything here is exact integer arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace n2v {
+
+constexpr uint32_t kC16 = 65536u;  // alpha = 1 (common neighbour) in Q16
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// multiply-xor bijection with the key advanced by the Weyl constants between
+// rounds.  Key = (seed lo, seed hi), counter = (step, wid lo, wid hi, 0); the
+// 64-bit draw is word0 | word1 << 32.
+__device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint32_t step, uint64_t wid) {
+  uint32_t x0 = step, x1 = (uint32_t)wid, x2 = (uint32_t)(wid >> 32), x3 = 0u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t lo0 = m0 * x0, hi0 = __umulhi(m0, x0);
+    uint32_t lo1 = m1 * x2, hi1 = __umulhi(m1, x2);
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return (uint64_t)x0 | ((uint64_t)x1 << 32);
+}
+
+// floor(r * total / 2^64): uniform in [0, total) (step 3 of the sampler).
+__device__ __forceinline__ uint64_t scale_draw(uint64_t r, uint64_t total) {
+  return __umul64hi(r, total);
+}
+
+// ---------------------------------------------------------------------------
+// Sub-wave groups of G lanes (G divides 64).  Control flow is uniform inside
+// a group, so the cross-lane reads below only touch active lanes.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ uint64_t grp_sum(uint64_t x) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t grp_incl_scan(uint64_t x, int gl) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    uint64_t y = __shfl_up(x, (unsigned)o, G);
+    if (gl >= o) x += y;
+  }
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t grp_bcast(uint64_t x, int src) {
+  return __shfl(x, src, G);
+}
+
+template <int G>
+__device__ __forceinline__ int32_t grp_bcast_i32(int32_t x, int src) {
+  return __shfl(x, src, G);
+}
+
+// Mask of the lanes of this group (bit i = group lane i) whose pred is true.
+template <int G>
+__device__ __forceinline__ uint64_t grp_ballot(bool pred, int gbase) {
+  uint64_t m = __ballot(pred);
+  if (G == 64) return m;
+  return (m >> gbase) & ((1ull << G) - 1ull);
+}
+
+// First index j in [0, d) with R[j] > T (R non-decreasing); d if none.
+template <typename RT>
+__device__ __forceinline__ uint32_t upper_bound_gt(const RT* R, uint32_t d, uint64_t T) {
+  uint32_t lo = 0, hi = d;
+  while (lo < hi) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((uint64_t)R[mid] > T) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+// First index j in [0, d) with D[j] >= x; d if none.
+__device__ __forceinline__ uint32_t lower_bound_i32(const int32_t* D, uint32_t d, int32_t x) {
+  uint32_t lo = 0, hi = d;
+  while (lo < hi) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if (D[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace n2v

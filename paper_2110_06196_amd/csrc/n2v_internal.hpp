@@ -1,0 +1,74 @@
+// Internal interface between the host runtime (n2v_api.cpp) and the kernels
+// (n2v_walk.hip, n2v_prep.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace n2v {
+
+// Resident graph: borrowed CSR plus library-owned derived arrays.
+struct GraphDev {
+  const uint64_t* O = nullptr;  // [n+1]
+  const int32_t* D = nullptr;   // [m]
+  const uint32_t* W = nullptr;  // [m] or null (unweighted)
+  const void* R = nullptr;      // per-row inclusive weight prefix, [m], uint32 or uint64
+  uint32_t r_bytes = 0;         // 0 (unweighted), 4 or 8
+  int64_t n = 0;
+  uint64_t m = 0;
+};
+
+// One walk request as the kernels see it.
+struct WalkArgs {
+  GraphDev g;
+  const int32_t* starts;
+  uint64_t ns;
+  uint64_t nwalks;  // ns * walks_per_start
+  uint32_t L;
+  uint32_t second_order;  // 0: first order (alpha = 1 everywhere)
+  uint32_t P16, Q16;
+  uint64_t seed;
+  uint64_t wid_base;
+  int32_t* Y;
+  int32_t* lens;
+};
+
+// Which kernel family serves a request.
+enum class Path : int {
+  kFirstOrder = 0,  // lane per walker: unweighted multiply-shift / weighted prefix search
+  kReturnOnly = 1,  // node2vec with Q16 == 65536: lane per walker, O(log d) per step
+  kGeneric = 2      // node2vec with Q16 != 65536: G lanes per walker, streamed rows
+};
+
+struct LaunchCfg {
+  int lanes_per_walker = 16;  // generic path
+  int lds_tile = 512;         // entries of N(t) per walker kept in LDS
+  uint32_t hub_threshold = 0;
+  int grid_blocks = 0;        // 0 = derive from occupancy
+  bool no_asym = false;
+};
+
+// Device facts used to size grids.
+struct DevInfo {
+  int device = 0;
+  int cus = 0;
+  size_t lds_per_block_max = 0;
+};
+
+hipError_t launch_walks(const WalkArgs& a, Path path, const LaunchCfg& cfg, const DevInfo& di,
+                        hipStream_t st);
+
+// Graph preparation.  stats: [0] error flags, [1] max degree, [2] max row sum,
+// [3] sum of degree^2 (device uint64[4], zeroed by the caller).
+hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+                                 const uint32_t* W, uint64_t* stats, hipStream_t st);
+hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,
+                             uint32_t r_bytes, hipStream_t st);
+
+enum : uint64_t {
+  kErrOffsets = 1,   // O[0] != 0, O not monotone or O[n] != m
+  kErrOrder = 2,     // a row not strictly increasing
+  kErrRange = 4      // destination outside [0, n)
+};
+
+}  // namespace n2v

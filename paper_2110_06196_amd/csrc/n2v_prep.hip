@@ -1,0 +1,118 @@
+// Graph preparation kernels: CSR validation, statistics and the per-row
+// inclusive weight prefix used by the O(log d) sampling paths.
+//
+// The CSR store with sorted rows is the paper's default adjacency structure
+// (Methods, "Succinct data structures" and "Available data-structure
+// trade-offs"); the degree of v is offsets[v+1] - offsets[v].
+#include "n2v_device.hpp"
+#include "n2v_internal.hpp"
+
+namespace n2v {
+
+namespace {
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, 64);
+  return x;
+}
+
+// One wavefront per row (grid-stride).  Rows whose offsets are inconsistent
+// are flagged and never dereferenced.
+__global__ __launch_bounds__(256) void k_validate_stats(const uint64_t* __restrict__ O, int64_t n,
+                                                        const int32_t* __restrict__ D, uint64_t m,
+                                                        const uint32_t* __restrict__ W,
+                                                        unsigned long long* __restrict__ stats) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  uint64_t err = 0, maxd = 0, maxs = 0, sumd2 = 0;
+  if (wave == 0 && (O[0] != 0 || O[n] != m)) err |= kErrOffsets;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const uint64_t lo = O[v], hi = O[v + 1];
+    if (hi < lo || hi > m) {
+      err |= kErrOffsets;
+      continue;
+    }
+    uint64_t s = 0;
+    for (uint64_t e = lo + lane; e < hi; e += 64) {
+      const int32_t x = D[e];
+      if (x < 0 || (int64_t)x >= n) err |= kErrRange;
+      if (e > lo && D[e - 1] >= x) err |= kErrOrder;
+      s += W ? (uint64_t)W[e] : 1ull;
+    }
+    s = wave_sum_u64(s);
+    const uint64_t d = hi - lo;
+    maxd = d > maxd ? d : maxd;
+    maxs = s > maxs ? s : maxs;
+    sumd2 += d * d;
+  }
+  err = wave_or_u64(err);
+  if (lane == 0) {
+    if (err) atomicOr(stats + 0, (unsigned long long)err);
+    atomicMax(stats + 1, (unsigned long long)maxd);
+    atomicMax(stats + 2, (unsigned long long)maxs);
+    atomicAdd(stats + 3, (unsigned long long)sumd2);
+  }
+}
+
+// R[e] = sum of W over row entries up to and including e (row-local).
+template <typename RT>
+__global__ __launch_bounds__(256) void k_row_prefix(const uint64_t* __restrict__ O, int64_t n,
+                                                    const uint32_t* __restrict__ W,
+                                                    RT* __restrict__ R) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const uint64_t lo = O[v], hi = O[v + 1];
+    uint64_t carry = 0;
+    for (uint64_t base = lo; base < hi; base += 64) {
+      const uint64_t e = base + lane;
+      uint64_t x = e < hi ? (uint64_t)W[e] : 0ull;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(x, (unsigned)o, 64);
+        if (lane >= o) x += y;
+      }
+      if (e < hi) R[e] = (RT)(carry + x);
+      carry += __shfl(x, 63, 64);
+    }
+  }
+}
+
+int prep_blocks(int64_t n) {
+  int64_t waves = n;  // one wave per row
+  int64_t blocks = (waves + 3) / 4;
+  if (blocks > 256 * 32) blocks = 256 * 32;
+  if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+}  // namespace
+
+hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+                                 const uint32_t* W, uint64_t* stats, hipStream_t st) {
+  hipLaunchKernelGGL(k_validate_stats, dim3(prep_blocks(n)), dim3(256), 0, st, O, n, D, m, W,
+                     (unsigned long long*)stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,
+                             uint32_t r_bytes, hipStream_t st) {
+  if (r_bytes == 4)
+    hipLaunchKernelGGL(k_row_prefix<uint32_t>, dim3(prep_blocks(n)), dim3(256), 0, st, O, n, W,
+                       (uint32_t*)R);
+  else
+    hipLaunchKernelGGL(k_row_prefix<uint64_t>, dim3(prep_blocks(n)), dim3(256), 0, st, O, n, W,
+                       (uint64_t*)R);
+  return hipGetLastError();
+}
+
+}  // namespace n2v
