@@ -80,17 +80,23 @@ typedef struct {
 /* Launch tuning.  Zero fields mean "automatic".  Tuning never changes a walk:
  * every setting produces bit-identical output. */
 typedef struct {
-  uint32_t lanes_per_walker; /* generic node2vec path: 4, 8, 16, 32 or 64 lanes per walker */
-  uint32_t hub_threshold;    /* degree above which a step uses the whole-wavefront hub path;
-                                UINT32_MAX disables it */
-  uint32_t lds_tile;         /* entries of the previous node's row kept in LDS per walker */
+  uint32_t lanes_per_walker; /* node2vec (1/q != 1) path: 4, 8, 16, 32 or 64 lanes per walker */
+  uint32_t lds_tile;         /* entries of the previous node's row staged in LDS per walker */
+  uint32_t list_cap;         /* entries of the common-neighbour list kept in LDS per walker */
+  uint32_t route;            /* N2V_ROUTE_*: how a node2vec step with 1/q != 1 classifies */
   uint32_t flags;            /* N2V_TUNE_* bits */
 } n2v_tuning_t;
 
 enum {
-  N2V_TUNE_GENERIC_ONLY = 1u,  /* route every step through the generic node2vec path
-                                  (no first-order / q == 1 specialisations) */
-  N2V_TUNE_NO_ASYMMETRIC = 2u  /* hub path: always stream the row, never probe N(t) into N(v) */
+  N2V_ROUTE_AUTO = 0,     /* per step, the cheaper of PROBE and STREAM by a latency estimate */
+  N2V_ROUTE_TWO_PASS = 1, /* stream the biased weights of N(v) twice (block sums, then one block) */
+  N2V_ROUTE_PROBE = 2,    /* bisect every node of N(t) into N(v) to list the common neighbours */
+  N2V_ROUTE_STREAM = 3    /* stream N(v) and test each candidate against N(t) */
+};
+
+enum {
+  N2V_TUNE_GENERIC_ONLY = 1u  /* route every step through the G-lanes-per-walker kernel
+                                 (no first-order / 1/q == 1 lane-per-walker specialisations) */
 };
 
 /* ---------------------------------------------------------------------------

@@ -22,7 +22,8 @@ N2V_OK, N2V_PENDING = 0, 1
 N2V_ERR_INVALID_ARG, N2V_ERR_UNSORTED, N2V_ERR_OVERFLOW = -1, -2, -3
 N2V_ERR_NOMEM, N2V_ERR_HIP, N2V_ERR_BAD_HANDLE, N2V_ERR_REJECTED = -4, -5, -6, -7
 N2V_FIRST_ORDER, N2V_NODE2VEC = 0, 1
-N2V_TUNE_GENERIC_ONLY, N2V_TUNE_NO_ASYMMETRIC = 1, 2
+N2V_TUNE_GENERIC_ONLY = 1
+N2V_ROUTE_AUTO, N2V_ROUTE_TWO_PASS, N2V_ROUTE_PROBE, N2V_ROUTE_STREAM = 0, 1, 2, 3
 
 _STATUS = {
     0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "UNSORTED", -3: "OVERFLOW", -4: "NOMEM",
@@ -44,8 +45,8 @@ class GraphInfo(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("lanes_per_walker", ctypes.c_uint32), ("hub_threshold", ctypes.c_uint32),
-                ("lds_tile", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+    _fields_ = [("lanes_per_walker", ctypes.c_uint32), ("lds_tile", ctypes.c_uint32),
+                ("list_cap", ctypes.c_uint32), ("route", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class RequestDesc(ctypes.Structure):
@@ -156,11 +157,12 @@ def n2v_graph_release(g: int) -> None:
     _check(lib().n2v_graph_release(g))
 
 
-def n2v_set_tuning(lanes_per_walker=0, hub_threshold=0, lds_tile=0, flags=0, reset=False) -> None:
+def n2v_set_tuning(lanes_per_walker=0, lds_tile=0, list_cap=0, route=0, flags=0, reset=False) -> None:
+    """Process-wide launch tuning (zero = automatic); reset=True restores automatic."""
     if reset:
         _check(lib().n2v_set_tuning(None))
         return
-    t = Tuning(lanes_per_walker, hub_threshold, lds_tile, flags)
+    t = Tuning(lanes_per_walker, lds_tile, list_cap, route, flags)
     _check(lib().n2v_set_tuning(ctypes.byref(t)))
 
 

@@ -89,17 +89,22 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
   const double ed = gr.n_entries ? (double)gr.sum_deg_sq / (double)gr.n_entries : 0.0;
   c.lanes_per_walker = ed > 256 ? 64 : (ed > 48 ? 32 : 16);
   c.lds_tile = c.lanes_per_walker == 64 ? 1024 : (c.lanes_per_walker == 32 ? 512 : 256);
-  c.hub_threshold = 0;
+  c.list_cap = c.lanes_per_walker == 64 ? 512 : (c.lanes_per_walker == 32 ? 256 : 128);
+  c.mode = 0;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_tune_set) {
     if (g_tune.lanes_per_walker) c.lanes_per_walker = (int)g_tune.lanes_per_walker;
     if (g_tune.lds_tile) c.lds_tile = (int)g_tune.lds_tile;
-    if (g_tune.hub_threshold) c.hub_threshold = g_tune.hub_threshold;
-    c.no_asym = (g_tune.flags & N2V_TUNE_NO_ASYMMETRIC) != 0;
+    if (g_tune.list_cap) c.list_cap = (int)g_tune.list_cap;
+    c.mode = (int)g_tune.route;
   }
   // keep the per-block LDS inside the hardware limit
   const size_t gpb = 256 / (size_t)c.lanes_per_walker;
-  while (c.lds_tile > 1 && gpb * 2 * (size_t)c.lds_tile * 4 > di.lds_per_block_max) c.lds_tile /= 2;
+  auto bytes = [&]() { return gpb * (2 * (size_t)c.lds_tile + 2 * (size_t)c.list_cap) * 4; };
+  while (bytes() > di.lds_per_block_max && (c.lds_tile > 1 || c.list_cap > 1)) {
+    if (c.lds_tile >= c.list_cap && c.lds_tile > 1) c.lds_tile /= 2;
+    else c.list_cap /= 2;
+  }
   return c;
 }
 
@@ -268,7 +273,10 @@ int n2v_set_tuning(const n2v_tuning_t* tuning) {
     const uint32_t g = tuning->lanes_per_walker;
     if (g != 0 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
       return fail(N2V_ERR_INVALID_ARG, "lanes_per_walker must be 4, 8, 16, 32 or 64");
-    if (tuning->lds_tile > (1u << 16)) return fail(N2V_ERR_INVALID_ARG, "lds_tile too large");
+    if (tuning->lds_tile > (1u << 16) || tuning->list_cap > (1u << 16))
+      return fail(N2V_ERR_INVALID_ARG, "lds_tile / list_cap too large");
+    if (tuning->route > N2V_ROUTE_STREAM) return fail(N2V_ERR_INVALID_ARG, "unknown route");
+    if (tuning->flags & ~(uint32_t)N2V_TUNE_GENERIC_ONLY) return fail(N2V_ERR_INVALID_ARG, "unknown flags");
   }
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune_set = tuning != nullptr;

@@ -37,15 +37,15 @@ struct WalkArgs {
 enum class Path : int {
   kFirstOrder = 0,  // lane per walker: unweighted multiply-shift / weighted prefix search
   kReturnOnly = 1,  // node2vec with Q16 == 65536: lane per walker, O(log d) per step
-  kGeneric = 2      // node2vec with Q16 != 65536: G lanes per walker, streamed rows
+  kGeneric = 2      // node2vec with Q16 != 65536: G lanes per walker
 };
 
 struct LaunchCfg {
   int lanes_per_walker = 16;  // generic path
   int lds_tile = 512;         // entries of N(t) per walker kept in LDS
-  uint32_t hub_threshold = 0;
+  int list_cap = 256;         // common-neighbour list entries per walker in LDS
+  int mode = 0;               // 0 auto, 1 two-pass streaming, 2 probe N(t), 3 stream N(v)
   int grid_blocks = 0;        // 0 = derive from occupancy
-  bool no_asym = false;
 };
 
 // Device facts used to size grids.

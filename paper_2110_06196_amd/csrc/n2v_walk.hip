@@ -19,13 +19,21 @@
 //      - node2vec with 1/q == 1:  only x == t is re-weighted, so
 //        B_j = C16 R_j + (P16 - C16) w_t [j >= pos(t)]  (mod 2^64, exact since
 //        B_j < 2^64), searched by bisection; pos(t) by bisection for t in N(v).
-//  * k_walk_group  G lanes per walker (node2vec with 1/q != 1): the row of v is
-//      streamed in chunks of G candidates; each candidate is classified
-//      return / common / far against N(t), which sits in LDS when the previous
-//      row was short enough to stage (ping-pong buffers), else is probed in
-//      global memory; uint64 group reductions give block sums, and a second
-//      pass over a single block finds the selected index with a group scan and
-//      a ballot.
+//  * k_walk_n2v    G lanes per walker (node2vec with 1/q != 1).  With R the row
+//      prefix of v, a special list C of the positions of common neighbours
+//      (x in N(t), x != t; the in-out bias is 1 exactly there, Eq. 3 and the
+//      set difference N(v) minus N(t) that follows it) and the position pt of
+//      t (return bias), the cumulative sum is
+//        B_j = Q16 R_j + (C16 - Q16) sum_{c in C, c <= j} w_c + (P16 - Q16) w_t [j >= pt]
+//      (mod 2^64; exact because the true B_j < 2^64).  C is built by the cheaper
+//      of two equivalent routes: probe every y in N(t) into N(v) by bisection
+//      (short N(t), long N(v): the typical leaf-to-hub step), or stream N(v)
+//      and test each x against N(t) (kept in LDS when the previous row fit a
+//      ping-pong tile, else bisected in global memory).  The draw is then
+//      located by a ballot over B at the listed positions and a G-ary search
+//      of the segment between two of them.  If C overflows its LDS list the
+//      step streams the biased weights in two passes instead (block sums, then
+//      a scan of one block).
 #include "n2v_device.hpp"
 #include "n2v_internal.hpp"
 
@@ -119,20 +127,58 @@ __device__ __forceinline__ bool global_contains(const int32_t* __restrict__ A, u
   return lo < n && A[lo] == x;
 }
 
-template <int G, bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_walk_group(WalkArgs a, int tile) {
+// ---------------------------------------------------------------------------
+// node2vec kernel: G lanes per walker.
+// ---------------------------------------------------------------------------
+enum { kModeAuto = 0, kModeTwoPass = 1, kModeProbe = 2, kModeStream = 3 };
+
+__device__ __forceinline__ uint32_t ceil_log2p1(uint32_t x) {  // ceil(log2(x + 1))
+  return 32u - (uint32_t)__clz(x);
+}
+
+// First j in [lo, hi) with pred(j) (pred monotone in j); hi if none.  Group
+// cooperative: each round the G lanes probe G evenly spaced points.
+template <int G, typename P>
+__device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl, int gbase, P pred) {
+  while (hi - lo > (uint32_t)G) {
+    const uint32_t step = (hi - lo + G - 1) / G;
+    const uint32_t j = lo + (uint32_t)(gl + 1) * step - 1;
+    const bool real = j < hi;
+    const bool pr = real ? pred(j) : true;
+    const uint64_t m = grp_ballot<G>(pr, gbase);
+    if (m == 0) return hi;  // lane G-1 probed hi - 1 and it is false
+    const int f = __ffsll((unsigned long long)m) - 1;
+    const uint32_t jf = (uint32_t)grp_bcast_i32<G>((int32_t)j, f);
+    lo = lo + (uint32_t)f * step;  // every probe below lane f is false
+    if (jf < hi) hi = jf;          // the probe of lane f is true
+  }
+  const uint32_t j = lo + (uint32_t)gl;
+  const bool pr = j < hi && pred(j);
+  const uint64_t m = grp_ballot<G>(pr, gbase);
+  return m ? lo + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
+}
+
+template <int G, bool WEIGHTED, typename RT>
+__global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
   extern __shared__ int32_t lds[];
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);
   const int gib = threadIdx.x / G;
   const int gpb = blockDim.x / G;
-  int32_t* const bufA = lds + (size_t)gib * 2 * tile;
+  int32_t* const bufA = lds + (size_t)gib * (2 * tile + 2 * cap);
   int32_t* const bufB = bufA + tile;
+  uint32_t* const lpos = (uint32_t*)(bufB + tile);
+  uint32_t* const lw = lpos + cap;
   const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const uint32_t* __restrict__ W = a.g.W;
+  const RT* __restrict__ R = (const RT*)a.g.R;
+  const uint64_t lt_mask = (gl == 0) ? 0ull : ((~0ull) >> (64 - gl));  // group lanes below gl
+  const uint64_t P16 = a.P16, Q16 = a.Q16;
+  const uint64_t cdel = (uint64_t)kC16 - Q16;  // common minus far, mod 2^64
+  const uint64_t rdel = P16 - Q16;             // return minus far, mod 2^64
 
   for (uint64_t w = (uint64_t)blockIdx.x * gpb + gib; w < a.nwalks; w += ngroups) {
     int32_t* __restrict__ row = a.Y + w * a.L;
@@ -153,64 +199,212 @@ __global__ __launch_bounds__(256) void k_walk_group(WalkArgs a, int tile) {
       for (uint32_t s = 1; s < a.L; ++s) {
         const uint64_t lo = O[v];
         const uint32_t d = (uint32_t)(O[v + 1] - lo);
-        if (d == 0) break;
-        const bool second = a.second_order && t >= 0;
-        const bool stage = d <= (uint32_t)tile;
-        const uint32_t nc = (d + G - 1) / G;   // chunks of G candidates
-        const uint32_t bs = (nc + G - 1) / G;  // chunks per block (at most G blocks)
+        if (d == 0) break;  // dead end
+        const uint64_t r = philox_draw(a.seed, s, wid);
+        auto Rv = [&](uint32_t j) -> uint64_t {
+          return WEIGHTED ? (uint64_t)R[lo + j] : (uint64_t)j + 1ull;
+        };
+        const uint64_t S = Rv(d - 1);  // row weight sum
+        uint32_t jsel = 0xFFFFFFFFu;
+        bool staged = false;
+        bool stop = false;
 
-        auto alpha = [&](int32_t x) -> uint64_t {
-          if (!second) return 1ull;
-          if (x == t) return (uint64_t)a.P16;
-          const bool common = t_in_lds ? lds_contains(cur, td, x) : global_contains(D + tlo, td, x);
-          return common ? (uint64_t)kC16 : (uint64_t)a.Q16;
+        auto member = [&](int32_t x) -> bool {
+          return t_in_lds ? lds_contains(cur, td, x) : global_contains(D + tlo, td, x);
         };
 
-        // Pass 1: block sums of the biased weights; lane k keeps block k.
-        uint64_t acc = 0, blk = 0;
-        for (uint32_t c = 0; c < nc; ++c) {
-          const uint32_t j = c * G + gl;
-          if (j < d) {
-            const int32_t x = D[lo + j];
-            if (stage) nxt[j] = x;
-            const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + j] : 1ull;
-            acc += wt * alpha(x);
+        // Two-pass streaming over the biased weights (also the fallback when
+        // the list of common neighbours does not fit in LDS).
+        auto two_pass = [&]() {
+          const uint32_t nc = (d + G - 1) / G;
+          const uint32_t bs = (nc + G - 1) / G;
+          const bool stg = d <= (uint32_t)tile;
+          auto alpha = [&](int32_t x) -> uint64_t {
+            if (x == t) return P16;
+            return member(x) ? (uint64_t)kC16 : Q16;
+          };
+          uint64_t acc = 0, blk = 0;
+          for (uint32_t c = 0; c < nc; ++c) {
+            const uint32_t j = c * G + gl;
+            if (j < d) {
+              const int32_t x = D[lo + j];
+              if (stg) nxt[j] = x;
+              const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + j] : 1ull;
+              acc += wt * alpha(x);
+            }
+            if ((c + 1) % bs == 0 || c + 1 == nc) {
+              const uint64_t sb = grp_sum<G>(acc);
+              if ((uint32_t)gl == c / bs) blk = sb;
+              acc = 0;
+            }
           }
-          if ((c + 1) % bs == 0 || c + 1 == nc) {
-            const uint64_t sb = grp_sum<G>(acc);
-            if ((uint32_t)gl == c / bs) blk = sb;
-            acc = 0;
+          staged = stg;
+          const uint64_t incl = grp_incl_scan<G>(blk, gl);
+          const uint64_t total = grp_bcast<G>(incl, G - 1);
+          if (total == 0) {
+            stop = true;
+            return;
           }
-        }
-        const uint64_t incl = grp_incl_scan<G>(blk, gl);
-        const uint64_t total = grp_bcast<G>(incl, G - 1);
-        if (total == 0) break;
-        const uint64_t T = scale_draw(philox_draw(a.seed, s, wid), total);
-        const uint64_t bm = grp_ballot<G>(incl > T, gbase);
-        const int kb = __ffsll((unsigned long long)bm) - 1;
-        uint64_t base = grp_bcast<G>(incl - blk, kb);
+          const uint64_t T = scale_draw(r, total);
+          const uint64_t bm = grp_ballot<G>(incl > T, gbase);
+          const int kb = __ffsll((unsigned long long)bm) - 1;
+          uint64_t base = grp_bcast<G>(incl - blk, kb);
+          const uint32_t cend = min((uint32_t)(kb + 1) * bs, nc);
+          for (uint32_t c = (uint32_t)kb * bs; c < cend; ++c) {
+            const uint32_t j = c * G + gl;
+            uint64_t b = 0;
+            if (j < d) {
+              const int32_t x = stg ? nxt[j] : D[lo + j];
+              const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + j] : 1ull;
+              b = wt * alpha(x);
+            }
+            const uint64_t inc = grp_incl_scan<G>(b, gl);
+            const uint64_t m2 = grp_ballot<G>(base + inc > T, gbase);
+            if (m2) {
+              jsel = c * G + (uint32_t)(__ffsll((unsigned long long)m2) - 1);
+              break;
+            }
+            base += grp_bcast<G>(inc, G - 1);
+          }
+        };
 
-        // Pass 2: rescan block kb only.
-        int32_t xsel = -1;
-        const uint32_t cend = min((uint32_t)(kb + 1) * bs, nc);
-        for (uint32_t c = (uint32_t)kb * bs; c < cend; ++c) {
-          const uint32_t j = c * G + gl;
-          uint64_t b = 0;
-          int32_t x = -1;
-          if (j < d) {
-            x = stage ? nxt[j] : D[lo + j];
-            const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + j] : 1ull;
-            b = wt * alpha(x);
+        if (!a.second_order || t < 0) {
+          // First-order step (also the first step of a node2vec walk).
+          if (S == 0) break;
+          const uint64_t T = scale_draw(r, S);
+          if (WEIGHTED) {
+            jsel = gary_first<G>(0u, d, gl, gbase, [&](uint32_t j) { return (uint64_t)R[lo + j] > T; });
+          } else {
+            jsel = (uint32_t)T;
           }
-          const uint64_t inc = grp_incl_scan<G>(b, gl);
-          const uint64_t m2 = grp_ballot<G>(base + inc > T, gbase);
-          if (m2) {
-            xsel = grp_bcast_i32<G>(x, __ffsll((unsigned long long)m2) - 1);
-            break;
+          if (a.second_order && d <= (uint32_t)tile) {
+            for (uint32_t j = gl; j < d; j += G) nxt[j] = D[lo + j];
+            staged = true;
           }
-          base += grp_bcast<G>(inc, G - 1);
+        } else {
+          int mode = mode_knob;
+          if (mode == kModeAuto) {
+            // dependent-latency estimate: global probe = 100, LDS probe = 15
+            const uint32_t probe = ((td + 1 + G - 1) / G) * ceil_log2p1(d) * 100u;
+            const uint32_t stream = ((d + G - 1) / G) * (100u + ceil_log2p1(td) * (t_in_lds ? 15u : 100u));
+            mode = probe < stream ? kModeProbe : kModeStream;
+          }
+          if (mode == kModeTwoPass) {
+            two_pass();
+          } else {
+            // Build the sorted list of positions j in N(v) whose candidate is a
+            // common neighbour (x in N(t), x != t), and the position of t.
+            uint32_t cnt = 0, pt = 0;
+            bool has_t = false;
+            uint64_t acc = 0;
+            auto append = [&](bool hit, uint32_t pos) {
+              const uint64_t m = grp_ballot<G>(hit, gbase);
+              if (hit) {
+                const uint32_t idx = cnt + (uint32_t)__popcll(m & lt_mask);
+                const uint32_t wv = WEIGHTED ? W[lo + pos] : 1u;
+                acc += wv;
+                if (idx < (uint32_t)cap) {
+                  lpos[idx] = pos;
+                  lw[idx] = wv;
+                }
+              }
+              cnt += (uint32_t)__popcll(m);
+            };
+            if (mode == kModeProbe) {
+              // keys: N(t) and, last, t itself (to find its position in N(v))
+              const uint32_t nk = td + 1;
+              for (uint32_t c = 0; c < nk; c += G) {
+                const uint32_t k = c + gl;
+                const bool act = k < nk;
+                const bool tkey = k == td;
+                int32_t y = t;
+                if (act && !tkey) y = t_in_lds ? cur[k] : D[tlo + k];
+                const bool probe_it = act && (tkey || y != t);
+                bool hit = false;
+                uint32_t pos = 0;
+                if (probe_it) {
+                  pos = lower_bound_i32(D + lo, d, y);
+                  hit = pos < d && D[lo + pos] == y;
+                }
+                const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
+                if (mt) {
+                  has_t = true;
+                  pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
+                }
+                append(hit && !tkey, pos);
+              }
+            } else {
+              const bool stg = d <= (uint32_t)tile;
+              for (uint32_t c = 0; c < d; c += G) {
+                const uint32_t j = c + gl;
+                const bool act = j < d;
+                int32_t x = 0;
+                if (act) {
+                  x = D[lo + j];
+                  if (stg) nxt[j] = x;
+                }
+                const bool isret = act && x == t;
+                const uint64_t mt = grp_ballot<G>(isret, gbase);
+                if (mt) {
+                  has_t = true;
+                  pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
+                }
+                append(act && !isret && member(x), j);
+              }
+              staged = stg;
+            }
+            // the list is read by other lanes of the group below
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (cnt > (uint32_t)cap) {
+              two_pass();  // list overflow: stream the biased weights instead
+            } else {
+              const uint64_t CW = grp_sum<G>(acc);
+              const uint64_t wt = has_t ? (WEIGHTED ? (uint64_t)W[lo + pt] : 1ull) : 0ull;
+              const uint64_t retw = rdel * wt;
+              const uint64_t total = Q16 * S + cdel * CW + retw;
+              if (total == 0) break;
+              const uint64_t T = scale_draw(r, total);
+              // B_j = Q16 R_j + cdel * (common weight up to j) + retw [j >= pt]
+              uint64_t E = 0, Eprev = CW;
+              uint32_t seg_lo = 0, seg_hi = d, lastpos = 0;
+              bool found = false;
+              for (uint32_t c = 0; c < cnt; c += G) {
+                const uint32_t k = c + gl;
+                const bool act = k < cnt;
+                const uint32_t p = act ? lpos[k] : 0u;
+                const uint64_t wk = act ? (uint64_t)lw[k] : 0ull;
+                const uint64_t inc = grp_incl_scan<G>(wk, gl);
+                const uint64_t Ek = E + inc;
+                const uint64_t Bk = Q16 * Rv(p) + cdel * Ek + ((has_t && p >= pt) ? retw : 0ull);
+                const uint64_t m = grp_ballot<G>(act && Bk > T, gbase);
+                if (m) {
+                  const int f = __ffsll((unsigned long long)m) - 1;
+                  Eprev = grp_bcast<G>(Ek - wk, f);
+                  seg_hi = (uint32_t)grp_bcast_i32<G>((int32_t)p, f);
+                  const uint32_t pprev = (uint32_t)grp_bcast_i32<G>((int32_t)p, f > 0 ? f - 1 : 0);
+                  seg_lo = f > 0 ? pprev + 1 : (c > 0 ? lastpos + 1 : 0u);
+                  found = true;
+                  break;
+                }
+                const uint32_t nact = min((uint32_t)G, cnt - c);
+                lastpos = (uint32_t)grp_bcast_i32<G>((int32_t)p, (int)nact - 1);
+                E += grp_bcast<G>(inc, G - 1);
+              }
+              if (!found) {
+                seg_lo = cnt > 0 ? lastpos + 1 : 0u;
+                seg_hi = d;
+                Eprev = CW;
+              }
+              const uint64_t base = cdel * Eprev;
+              jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
+                return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
+              });
+            }
+          }
         }
-        if (xsel < 0) break;  // unreachable: block kb's prefix exceeds T
+        if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
+        const int32_t xsel = D[lo + jsel];
 
         if ((uint32_t)gl == s % G) ob = xsel;
         if (s % G == G - 1) {
@@ -222,12 +416,14 @@ __global__ __launch_bounds__(256) void k_walk_group(WalkArgs a, int tile) {
         t = v;
         tlo = lo;
         td = d;
-        t_in_lds = stage;
-        int32_t* tmp = cur;
-        cur = nxt;
-        nxt = tmp;
+        t_in_lds = staged;
+        if (staged) {
+          int32_t* tmp = cur;
+          cur = nxt;
+          nxt = tmp;
+        }
         v = xsel;
-        // the staged row is read by other lanes of the group at the next step
+        // the staged row and the list are read by other lanes of the group
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
@@ -273,24 +469,24 @@ hipError_t go_lane(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, h
   return hipGetLastError();
 }
 
-template <int G, bool WEIGHTED>
-hipError_t go_group(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
-  auto k = k_walk_group<G, WEIGHTED>;
+template <int G, bool WEIGHTED, typename RT>
+hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
+  auto k = k_walk_n2v<G, WEIGHTED, RT>;
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * 2 * (size_t)cfg.lds_tile * sizeof(int32_t);
+  const size_t lds = (size_t)gpb * (2 * (size_t)cfg.lds_tile + 2 * (size_t)cfg.list_cap) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
-  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile);
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cfg.mode);
   return hipGetLastError();
 }
 
-template <bool WEIGHTED>
-hipError_t go_group_g(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
+template <bool WEIGHTED, typename RT>
+hipError_t go_n2v_g(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   switch (cfg.lanes_per_walker) {
-    case 4: return go_group<4, WEIGHTED>(a, cfg, di, st);
-    case 8: return go_group<8, WEIGHTED>(a, cfg, di, st);
-    case 16: return go_group<16, WEIGHTED>(a, cfg, di, st);
-    case 32: return go_group<32, WEIGHTED>(a, cfg, di, st);
-    default: return go_group<64, WEIGHTED>(a, cfg, di, st);
+    case 4: return go_n2v<4, WEIGHTED, RT>(a, cfg, di, st);
+    case 8: return go_n2v<8, WEIGHTED, RT>(a, cfg, di, st);
+    case 16: return go_n2v<16, WEIGHTED, RT>(a, cfg, di, st);
+    case 32: return go_n2v<32, WEIGHTED, RT>(a, cfg, di, st);
+    default: return go_n2v<64, WEIGHTED, RT>(a, cfg, di, st);
   }
 }
 
@@ -309,7 +505,8 @@ hipError_t launch_walks(const WalkArgs& a, Path path, const LaunchCfg& cfg, cons
       if (!weighted) return go_lane<kRetUnw, uint32_t>(a, cfg, di, st);
       return r64 ? go_lane<kRetW, uint64_t>(a, cfg, di, st) : go_lane<kRetW, uint32_t>(a, cfg, di, st);
     default:
-      return weighted ? go_group_g<true>(a, cfg, di, st) : go_group_g<false>(a, cfg, di, st);
+      if (!weighted) return go_n2v_g<false, uint32_t>(a, cfg, di, st);
+      return r64 ? go_n2v_g<true, uint64_t>(a, cfg, di, st) : go_n2v_g<true, uint32_t>(a, cfg, di, st);
   }
 }
 

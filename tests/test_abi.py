@@ -51,7 +51,9 @@ def test_argument_validation_without_device():
     assert L.n2v_graph_release(999) == n2v.N2V_ERR_BAD_HANDLE
     info = n2v.GraphInfo()
     assert L.n2v_graph_info(999, ctypes.byref(info)) == n2v.N2V_ERR_BAD_HANDLE
-    bad = n2v.Tuning(7, 0, 0, 0)
+    bad = n2v.Tuning(7, 0, 0, 0, 0)
+    assert L.n2v_set_tuning(ctypes.byref(bad)) == n2v.N2V_ERR_INVALID_ARG
+    bad = n2v.Tuning(16, 0, 0, 9, 0)
     assert L.n2v_set_tuning(ctypes.byref(bad)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_set_tuning(None) == n2v.N2V_OK
     assert L.n2v_walks_batched(None, 3, None) == n2v.N2V_ERR_INVALID_ARG

@@ -71,29 +71,45 @@ def test_fuzz_small_graphs():
         check(O, D, W, starts, int(rng.integers(1, 4)), L, kind, p, q, seed=it, base=int(rng.integers(0, 2**40)))
 
 
-def test_tuning_points_and_specialisations_identical():
-    """Every lanes-per-walker / LDS-tile setting and the generic-only route give
-    the same walks as the oracle (rows longer than the tile probe N(t) in
-    global memory; rows spanning many chunks exercise the block search)."""
-    O, D, W = synth.chung_lu(3000, 40000, 2.2, 20.0, 1500.0, (1, 100), seed=9)
+def _tuning_sweep(O, D, W, rows, L, cases, grid):
     n = len(O) - 1
     starts = np.arange(n)
-    rows = np.arange(0, n, 7)
     g, keep = upload(O, D, W)
-    Wn = None
-    gu, keepu = upload(O, D, None)
-    cases = [(NV, 0.25, 4.0), (NV, 2.0, 1.0), (NV, 1.0, 1.0), (FO, 1.0, 1.0), (NV, 0.5, 2.0)]
     for kind, p, q in cases:
-        for gg, ww in ((g, W), (gu, Wn)):
-            ref = check(O, D, ww, starts, 1, 30, kind, p, q, seed=3, g=gg, rows=rows)
-            for lanes in (4, 8, 16, 32, 64):
-                for tile in (1, 64, 2048):
-                    for flags in (0, n2v.N2V_TUNE_GENERIC_ONLY):
-                        n2v.n2v_set_tuning(lanes_per_walker=lanes, lds_tile=tile, flags=flags)
-                        Y, lens = run(gg, starts, 1, 30, kind, p, q, seed=3)
-                        assert np.array_equal(Y[rows], ref[0]) and np.array_equal(lens[rows], ref[1]), \
-                            (kind, p, q, lanes, tile, flags)
-            n2v.n2v_set_tuning(reset=True)
+        ref = check(O, D, W, starts, 1, L, kind, p, q, seed=3, g=g, rows=rows)
+        for lanes, tile, cap, route, flags in grid:
+            n2v.n2v_set_tuning(lanes_per_walker=lanes, lds_tile=tile, list_cap=cap, route=route, flags=flags)
+            Y, lens = run(g, starts, 1, L, kind, p, q, seed=3)
+            assert np.array_equal(Y[rows], ref[0]) and np.array_equal(lens[rows], ref[1]), \
+                (kind, p, q, lanes, tile, cap, route, flags)
+        n2v.n2v_set_tuning(reset=True)
+    n2v.n2v_graph_release(g)
+
+
+def test_tuning_points_and_specialisations_identical():
+    """Every lanes-per-walker / LDS tile / list capacity / route setting and the
+    generic-only route give the oracle's walks (tile 1 forces N(t) lookups in
+    global memory, list capacity 1 forces the two-pass fallback)."""
+    O, D, W = synth.chung_lu(3000, 40000, 2.2, 20.0, 1500.0, (1, 100), seed=9)
+    rows = np.arange(0, len(O) - 1, 7)
+    cases = [(NV, 0.25, 4.0), (NV, 2.0, 1.0), (NV, 1.0, 1.0), (FO, 1.0, 1.0), (NV, 0.5, 2.0)]
+    grid = [(lanes, tile, cap, route, flags)
+            for lanes in (4, 8, 16, 32, 64) for tile in (1, 2048) for cap in (1, 512)
+            for route in (0, 1, 2, 3) for flags in (0, n2v.N2V_TUNE_GENERIC_ONLY)]
+    for ww in (W, None):
+        _tuning_sweep(O, D, ww, rows, 30, cases, grid)
+
+
+def test_hub_rows_all_routes():
+    """Hubs of degree ~1e4: many chunks per block in the two-pass route, long
+    probe and stream lists, G-ary searches over long segments."""
+    O, D, W = synth.chung_lu(20000, 200000, 2.0, 20.0, 15000.0, (1, 1000), seed=12)
+    assert int((O[1:] - O[:-1]).max()) > 5000
+    rows = np.arange(0, len(O) - 1, 41)
+    cases = [(NV, 0.25, 4.0), (NV, 4.0, 0.25), (NV, 2.0, 1.0)]
+    grid = [(lanes, tile, cap, route, 0)
+            for lanes in (4, 64) for tile in (1, 4096) for cap in (1, 4096) for route in (1, 2, 3)]
+    _tuning_sweep(O, D, W, rows, 24, cases, grid)
 
 
 def test_ba_10k_full():
