@@ -88,8 +88,8 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
   LaunchCfg c;
   const double ed = gr.n_entries ? (double)gr.sum_deg_sq / (double)gr.n_entries : 0.0;
   c.lanes_per_walker = ed > 256 ? 64 : (ed > 48 ? 32 : 16);
-  c.lds_tile = c.lanes_per_walker == 64 ? 1024 : (c.lanes_per_walker == 32 ? 512 : 256);
-  c.list_cap = c.lanes_per_walker == 64 ? 512 : (c.lanes_per_walker == 32 ? 256 : 128);
+  c.lds_tile = c.lanes_per_walker == 64 ? 512 : (c.lanes_per_walker == 32 ? 512 : 256);
+  c.list_cap = c.lanes_per_walker == 64 ? 256 : (c.lanes_per_walker == 32 ? 256 : 128);
   c.mode = 0;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_tune_set) {

@@ -158,6 +158,11 @@ __device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl,
   return m ? lo + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
 }
 
+// Cooperative membership search of up to G keys at once: lane l < nk holds a
+// key; A[0..n) is sorted and strictly increasing (global memory).  The k =
+// G / nk lanes assigned to one key probe k evenly spaced points per round, so
+// a search takes about log_{k+1}(n) dependent loads instead of log2(n).
+// Returns, in lane l < nk, whether its key is in A and (if so) its index.
 template <int G, bool WEIGHTED, typename RT>
 __global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
   extern __shared__ int32_t lds[];
@@ -284,7 +289,7 @@ __global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap,
         } else {
           int mode = mode_knob;
           if (mode == kModeAuto) {
-            // dependent-latency estimate: global probe = 100, LDS probe = 15
+            // dependent-latency estimate: global load = 100, LDS load = 15
             const uint32_t probe = ((td + 1 + G - 1) / G) * ceil_log2p1(d) * 100u;
             const uint32_t stream = ((d + G - 1) / G) * (100u + ceil_log2p1(td) * (t_in_lds ? 15u : 100u));
             mode = probe < stream ? kModeProbe : kModeStream;
@@ -319,10 +324,9 @@ __global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap,
                 const bool tkey = k == td;
                 int32_t y = t;
                 if (act && !tkey) y = t_in_lds ? cur[k] : D[tlo + k];
-                const bool probe_it = act && (tkey || y != t);
-                bool hit = false;
                 uint32_t pos = 0;
-                if (probe_it) {
+                bool hit = false;
+                if (act) {
                   pos = lower_bound_i32(D + lo, d, y);
                   hit = pos < d && D[lo + pos] == y;
                 }
@@ -331,7 +335,8 @@ __global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap,
                   has_t = true;
                   pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
                 }
-                append(hit && !tkey, pos);
+                // a self-loop at t puts t in N(t): that candidate is a return, not common
+                append(hit && !tkey && y != t, pos);
               }
             } else {
               const bool stg = d <= (uint32_t)tile;
@@ -349,7 +354,13 @@ __global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap,
                   has_t = true;
                   pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
                 }
-                append(act && !isret && member(x), j);
+                bool in_t;
+                if (t_in_lds) {
+                  in_t = act && !isret && lds_contains(cur, td, x);
+                } else {
+                  in_t = act && !isret && global_contains(D + tlo, td, x);
+                }
+                append(act && !isret && in_t, j);
               }
               staged = stg;
             }

@@ -104,7 +104,7 @@ def test_hub_rows_all_routes():
     """Hubs of degree ~1e4: many chunks per block in the two-pass route, long
     probe and stream lists, G-ary searches over long segments."""
     O, D, W = synth.chung_lu(20000, 200000, 2.0, 20.0, 15000.0, (1, 1000), seed=12)
-    assert int((O[1:] - O[:-1]).max()) > 5000
+    assert int((O[1:] - O[:-1]).max()) > 4096  # > 64 chunks of 64: several chunks per block
     rows = np.arange(0, len(O) - 1, 41)
     cases = [(NV, 0.25, 4.0), (NV, 4.0, 0.25), (NV, 2.0, 1.0)]
     grid = [(lanes, tile, cap, route, 0)
