@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--runs", default="1,1;0.25,4", help="(p,q) pairs, ';'-separated")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--walk-len", type=int, default=100)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (PMC counter calibration)")
+    ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
+                                                              "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="write profiles/*.txt from rocprofv3 output directories and exit")
     return ap.parse_args()
 
 
@@ -71,47 +76,157 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_tag: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic_c2.txt")
-    if not os.path.exists(path):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_chung_lu_1m.txt")
+TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_chung_lu_1m.txt")
+KERNEL_OF_PATH = {"generic": "k_walk_n2v", "fo_weighted": "k_walk_lane", "return_only": "k_walk_lane"}
+COPY_BYTES = 1 << 30
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
+    if it was taken on the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
-    txt = open(path).read()
+    txt = open(TRAFFIC_FILE).read()
     m = re.search(r"source_hash:\s*(\w+)", txt)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(rf"^{re.escape(kernel_tag)}\s+hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
+    m = re.search(rf"^{re.escape(kernel)}\s+hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
     return float(m.group(1)) if m else None
 
 
-def algorithmic_bytes(torch, Y, lens, deg, variant: str) -> tuple[int, int]:
-    """(steps, bytes) the method must move for the walks in Y.
+def _csvs(d, suffix):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
 
-    Per transition taken from v (degree d): offsets 16 B, the output slot 4 B,
-      weighted first order (and node2vec with p = q = 1): the selected row
-        entry 4 B plus ceil(log2(d + 1)) prefix probes of 4 B;
-      node2vec with 1/q != 1: the whole row of v, destinations and weights, 8d B.
+
+def _pmc_per_kernel(d, counter):
+    """Mean counter value per dispatch, by kernel-name key."""
+    import csv
+    vals = {}
+    for f in _csvs(d, "counter_collection.csv"):
+        for row in csv.DictReader(open(f)):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row.get("Kernel_Name", "")
+            key = next((k for k in ("k_walk_n2v", "k_walk_lane", "copy") if k in name.lower() or
+                        (k == "copy" and "copy" in name.lower())), None)
+            if key is None:
+                key = name[:60]
+            vals.setdefault((key, row.get("Dispatch_Id")), 0.0)
+            vals[(key, row.get("Dispatch_Id"))] += float(row["Counter_Value"])
+    per = {}
+    for (key, _), v in vals.items():
+        per.setdefault(key, []).append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in per.items()}
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cmds):
+    import csv
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    lines = ["# rocprofv3 --kernel-trace --stats, 1M-node Chung-Lu node2vec workload",
+             f"# command: {cmds['trace']}", "# kernel | calls | total ns | average ns | min ns | max ns"]
+    for f in _csvs(trace_dir, "kernel_stats.csv"):
+        for row in csv.DictReader(open(f)):
+            lines.append(" | ".join([row["Name"][:110], row["Calls"], row["TotalDurationNs"],
+                                     row["AverageNs"], row["MinNs"], row["MaxNs"]]))
+    open(TRACE_FILE, "w").write("\n".join(lines) + "\n")
+    fetch = _pmc_per_kernel(fetch_dir, "FETCH_SIZE")
+    write = _pmc_per_kernel(write_dir, "WRITE_SIZE")
+    cf = _pmc_per_kernel(cal_fetch_dir, "FETCH_SIZE")
+    cw = _pmc_per_kernel(cal_write_dir, "WRITE_SIZE")
+    cal_f = max(cf.values(), key=lambda x: x[0])[0] if cf else None  # the 1 GiB copy dominates
+    cal_w = max(cw.values(), key=lambda x: x[0])[0] if cw else None
+    f_scale = COPY_BYTES / (cal_f * 1024.0) if cal_f else 1.0
+    w_scale = COPY_BYTES / (cal_w * 1024.0) if cal_w else 1.0
+    out = ["# HBM traffic per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB",
+           "# per dispatch), each scaled by what the same counter reads for a plain 1 GiB copy.",
+           f"# fetch command: {cmds['fetch']}", f"# write command: {cmds['write']}",
+           f"# calibration commands: {cmds['cal_fetch']} ; {cmds['cal_write']}",
+           f"source_hash: {kernel_source_hash()}",
+           f"copy_fetch_KiB: {cal_f}", f"copy_write_KiB: {cal_w}",
+           f"fetch_scale: {f_scale:.6f}", f"write_scale: {w_scale:.6f}"]
+    for k in sorted(set(fetch) | set(write)):
+        fk = fetch.get(k, (0.0, 0))[0] * 1024.0 * f_scale
+        wk = write.get(k, (0.0, 0))[0] * 1024.0 * w_scale
+        out.append(f"{k} fetch_bytes_per_launch: {fk:.6e} write_bytes_per_launch: {wk:.6e} "
+                   f"dispatches: {fetch.get(k, (0, 0))[1]}")
+        out.append(f"{k} hbm_bytes_per_launch: {fk + wk:.6e}")
+    open(TRAFFIC_FILE, "w").write("\n".join(out) + "\n")
+    print(open(TRACE_FILE).read())
+    print(open(TRAFFIC_FILE).read())
+
+
+def copy_calibration():
+    import torch
+    x = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+    x.fill_(1)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}))
+
+
+def _clog2p1(x, torch):
+    """ceil(log2(x + 1)) elementwise for int64 x >= 0."""
+    return torch.ceil(torch.log2((x + 1).to(torch.float64))).to(torch.int64)
+
+
+def algorithmic_bytes(torch, Y, lens, deg, variant: str) -> tuple[int, int]:
+    """(steps, bytes) the implemented method reads and writes for the walks in Y,
+    counting 4 bytes per 32-bit element touched (cache effects ignored).
+
+    Every transition from v (degree d_v): offsets of v 16 B, output slot 4 B,
+    selected destination 4 B.  Then
+      first order, weighted (also node2vec p = q = 1 and the first step of
+      every node2vec walk): ceil(log2(d_v + 1)) prefix probes of 4 B;
+      node2vec with 1/q != 1, later steps (previous node t, degree d_t): the row
+      sum 4 B, the return weight 4 B, the cheaper classification route
+        probe:  N(t) 4 d_t + d_t bisections into N(v), 4 ceil(log2(d_v + 1)) each
+        stream: N(v) 4 d_v + d_v bisections into N(t), 4 ceil(log2(d_t + 1)) each
+      and the final search over the prefix, 4 ceil(log2(d_v + 1)).
+      (Weights and prefix entries of common neighbours, a few per step, and
+      reuse of N(t) from LDS are not counted.)
     """
     steps = int((lens.to(torch.int64) - 1).clamp(min=0).sum().item())
     total = 0
-    chunk = 1 << 20
+    chunk = 1 << 19
     for r0 in range(0, Y.shape[0], chunk):
         y = Y[r0:r0 + chunk]
-        src = y[:, :-1]
         taken = (y[:, 1:] >= 0)
-        d = deg[src.clamp(min=0).to(torch.int64)].to(torch.int64)
-        if variant == "fo_weighted":
-            probes = torch.ceil(torch.log2((d + 1).to(torch.float64))).to(torch.int64)
-            b = 16 + 4 + 4 + 4 * probes
-        else:
-            b = 16 + 4 + 8 * d
+        dv = deg[y[:, :-1].clamp(min=0).to(torch.int64)]
+        lv = _clog2p1(dv, torch)
+        b = 24 + 4 * lv
+        if variant == "generic":
+            dt = deg[y[:, :-2].clamp(min=0).to(torch.int64)]
+            dv2 = dv[:, 1:]
+            lv2 = lv[:, 1:]
+            probe = 4 * dt + 4 * dt * lv2
+            stream = 4 * dv2 + 4 * dv2 * _clog2p1(dt, torch)
+            b2 = 24 + 8 + torch.minimum(probe, stream) + 4 * lv2
+            b = torch.cat([b[:, :1], b2], dim=1)
         total += int((b * taken).sum().item())
     return steps, total
 
 
 def main():
     args = parse()
+    if args.summarize_profiles:
+        t = "cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- " \
+            "python3 /root/repo/bench.py --steps 2 --warmup 0 --cpu-seconds 0"
+        f = "cd /tmp && rocprofv3 --pmc {c} --output-format csv -d <dir> -o run -- " \
+            "python3 /root/repo/bench.py --steps 1 --warmup 0 --cpu-seconds 0"
+        c = "cd /tmp && rocprofv3 --pmc {c} --output-format csv -d <dir> -o run -- " \
+            "python3 /root/repo/bench.py --copy-calibration"
+        summarize_profiles(*args.summarize_profiles, cmds={
+            "trace": t, "fetch": f.format(c="FETCH_SIZE"), "write": f.format(c="WRITE_SIZE"),
+            "cal_fetch": c.format(c="FETCH_SIZE"), "cal_write": c.format(c="WRITE_SIZE")})
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -170,13 +285,13 @@ def main():
         Y, lens = outs[i]
         ms = float(np.mean([ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)]))
         variant = "fo_weighted" if (p == 1.0 and q == 1.0) else ("return_only" if q == 1.0 else "generic")
-        steps, alg = algorithmic_bytes(torch, Y, lens, deg, variant if variant != "return_only" else "fo_weighted")
+        steps, alg = algorithmic_bytes(torch, Y, lens, deg, "generic" if variant == "generic" else "fo_weighted")
         total_steps += steps
         kernels.append({"p": p, "q": q, "path": variant, "mean_ms": ms, "steps": steps,
                         "alg_bytes": alg, "steps_per_s": steps / (ms / 1e3),
                         "alg_GBps": alg / (ms / 1e3) / 1e9})
     dom = max(kernels, key=lambda k: k["mean_ms"])
-    traffic = traffic_from_profiles(f"p{dom['p']:g}_q{dom['q']:g}")
+    traffic = traffic_from_profiles(KERNEL_OF_PATH[dom["path"]])
     value = total_steps * args.steps / t_total
 
     # CPU baseline: the oracle on an evenly spaced sample of the same walks.
