@@ -170,6 +170,32 @@ typedef struct {
 
 int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip_stream);
 
+/* Reusable batch plan: the request and chunk tables are uploaded once, the
+ * launch shape (lanes per walker, LDS tile, list capacity) is chosen by timing
+ * candidate shapes on a sample of the chunks (N2V_BATCH_AUTOTUNE; any shape
+ * yields the same walks, so the sample's outputs are simply rewritten), and
+ * the counter reset plus the persistent kernel are captured once into a
+ * hipGraph that n2v_batch_launch replays on hip_stream.  The caller keeps the
+ * graphs and the device buffers named in reqs alive until n2v_batch_destroy.
+ * n2v_batch_create is synchronous (it may launch the autotuning samples on an
+ * internal stream). */
+typedef uint64_t n2v_batch; /* opaque, 0 = invalid */
+enum { N2V_BATCH_AUTOTUNE = 1u };
+typedef struct {
+  uint32_t n_requests;
+  uint32_t n_chunks;
+  uint32_t lanes_per_walker; /* chosen launch shape */
+  uint32_t lds_tile;
+  uint32_t list_cap;
+  uint32_t reserved;
+  uint64_t n_walks;
+  double est_cost;           /* estimated work units (walk steps x per-step cost factor) */
+} n2v_batch_info_t;
+int n2v_batch_create(const n2v_request_desc_t* reqs, uint32_t n_reqs, uint32_t flags, n2v_batch* out);
+int n2v_batch_launch(n2v_batch b, void* hip_stream);
+int n2v_batch_info(n2v_batch b, n2v_batch_info_t* out);
+int n2v_batch_destroy(n2v_batch b);
+
 /* ---------------------------------------------------------------------------
  * Serving: resident graphs, requests admitted by memory footprint, continuous
  * batching (requests that arrive while others run are started as slots and
@@ -194,6 +220,11 @@ typedef struct {
   uint64_t t_arrival_ns, t_admit_ns, t_start_ns, t_done_ns; /* CLOCK_MONOTONIC */
 } n2v_result_t;
 
+/* n2v_server_create: `reserved` must be NULL.  Work runs on an internal stream
+ * in bounded quanta: each quantum is one launch of the persistent queue kernel
+ * over chunks of every admitted request (at most quantum_us of estimated work),
+ * and newly admitted requests join the next quantum.  No kernel ever waits on
+ * the host. */
 int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, void* reserved,
                       n2v_server* out);
 int n2v_server_add_graph(n2v_server s, n2v_graph g);

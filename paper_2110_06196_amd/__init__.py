@@ -24,6 +24,7 @@ N2V_ERR_NOMEM, N2V_ERR_HIP, N2V_ERR_BAD_HANDLE, N2V_ERR_REJECTED = -4, -5, -6, -
 N2V_FIRST_ORDER, N2V_NODE2VEC = 0, 1
 N2V_TUNE_GENERIC_ONLY = 1
 N2V_ROUTE_AUTO, N2V_ROUTE_TWO_PASS, N2V_ROUTE_PROBE, N2V_ROUTE_STREAM = 0, 1, 2, 3
+N2V_BATCH_AUTOTUNE = 1
 
 _STATUS = {
     0: "OK", 1: "PENDING", -1: "INVALID_ARG", -2: "UNSORTED", -3: "OVERFLOW", -4: "NOMEM",
@@ -58,6 +59,13 @@ class RequestDesc(ctypes.Structure):
                 ("d_walks", ctypes.c_void_p), ("d_lens", ctypes.c_void_p)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_requests", ctypes.c_uint32), ("n_chunks", ctypes.c_uint32),
+                ("lanes_per_walker", ctypes.c_uint32), ("lds_tile", ctypes.c_uint32),
+                ("list_cap", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("n_walks", ctypes.c_uint64), ("est_cost", ctypes.c_double)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("d_walks", ctypes.c_void_p), ("d_lens", ctypes.c_void_p),
                 ("n_walks", ctypes.c_uint64), ("steps", ctypes.c_uint64),
@@ -75,6 +83,10 @@ SIGNATURES = {
     "n2v_walks_node2vec": [_U64, _VP, _U64, _U32, _U32, _D, _D, _U64, _U64, _VP, _VP, _VP],
     "n2v_set_tuning": [ctypes.POINTER(Tuning)],
     "n2v_walks_batched": [ctypes.POINTER(RequestDesc), _U32, _VP],
+    "n2v_batch_create": [ctypes.POINTER(RequestDesc), _U32, _U32, ctypes.POINTER(_U64)],
+    "n2v_batch_launch": [_U64, _VP],
+    "n2v_batch_info": [_U64, ctypes.POINTER(BatchInfo)],
+    "n2v_batch_destroy": [_U64],
     "n2v_server_create": [_U64, _U32, _VP, ctypes.POINTER(_U64)],
     "n2v_server_add_graph": [_U64, _U64],
     "n2v_request_submit": [_U64, ctypes.POINTER(RequestDesc), _U64, ctypes.POINTER(_U64)],
@@ -218,6 +230,28 @@ def n2v_walks_batched(reqs, stream=None) -> None:
     _check(lib().n2v_walks_batched(arr, len(reqs), _stream(stream)))
 
 
+def n2v_batch_create(reqs, autotune: bool = True) -> int:
+    """Upload the request/chunk tables, pick the launch shape, capture a hipGraph."""
+    arr = (RequestDesc * len(reqs))(*reqs)
+    h = ctypes.c_uint64(0)
+    _check(lib().n2v_batch_create(arr, len(reqs), N2V_BATCH_AUTOTUNE if autotune else 0, ctypes.byref(h)))
+    return h.value
+
+
+def n2v_batch_launch(b: int, stream=None) -> None:
+    _check(lib().n2v_batch_launch(b, _stream(stream)))
+
+
+def n2v_batch_info(b: int) -> dict:
+    info = BatchInfo()
+    _check(lib().n2v_batch_info(b, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in BatchInfo._fields_}
+
+
+def n2v_batch_destroy(b: int) -> None:
+    _check(lib().n2v_batch_destroy(b))
+
+
 # ---------------------------------------------------------------------------
 # Serving
 # ---------------------------------------------------------------------------
@@ -231,6 +265,17 @@ def n2v_server_add_graph(s: int, g: int) -> None:
     _check(lib().n2v_server_add_graph(s, g))
 
 
+def host_request(graph: int, kind: int, starts_np, walks_per_start: int, walk_len: int, p=1.0, q=1.0,
+                 seed=0, walk_id_base=0):
+    """A RequestDesc whose starts point at host memory (for n2v_request_submit).
+    Returns (desc, keepalive): keep the second item alive until submit returns."""
+    import numpy as np
+    arr = np.ascontiguousarray(starts_np, dtype=np.int32)
+    d = RequestDesc(graph, kind, walks_per_start, walk_len, 0, float(p), float(q), seed, walk_id_base,
+                    arr.ctypes.data if arr.size else None, arr.size, None, None)
+    return d, arr
+
+
 def n2v_request_submit(s: int, desc: RequestDesc, arrival_ns: int) -> int:
     h = ctypes.c_uint64(0)
     _check(lib().n2v_request_submit(s, ctypes.byref(desc), arrival_ns, ctypes.byref(h)))
@@ -242,6 +287,34 @@ def n2v_request_poll(s: int, r: int):
     res = Result()
     rc = _check(lib().n2v_request_poll(s, r, ctypes.byref(res)))
     return None if rc == N2V_PENDING else res
+
+
+_hip_rt = None
+
+
+def _hip():
+    """The HIP runtime already loaded by torch (same soname, same instance)."""
+    global _hip_rt
+    if _hip_rt is None:
+        rt = ctypes.CDLL("libamdhip64.so.7")
+        rt.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        rt.hipMemcpy.restype = ctypes.c_int
+        _hip_rt = rt
+    return _hip_rt
+
+
+def result_tensors(res: Result, walk_len: int):
+    """Copy a finished request's server-owned walks / lens into new torch tensors."""
+    nw = int(res.n_walks)
+    Y = torch.empty((nw, walk_len), dtype=torch.int32, device="cuda")
+    lens = torch.empty(nw, dtype=torch.int32, device="cuda")
+    if nw:
+        torch.cuda.synchronize()
+        for dst, src, nbytes in ((Y.data_ptr(), res.d_walks, nw * walk_len * 4), (lens.data_ptr(), res.d_lens, nw * 4)):
+            rc = _hip().hipMemcpy(dst, src, nbytes, 3)  # device to device
+            if rc != 0:
+                raise N2VError(N2V_ERR_HIP, f"hipMemcpy failed ({rc})")
+    return Y, lens
 
 
 def n2v_request_release(s: int, r: int) -> None:

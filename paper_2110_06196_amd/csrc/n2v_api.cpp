@@ -108,6 +108,25 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
   return c;
 }
 
+void apply_tuning_override(LaunchCfg* c, const DevInfo& di) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_tune_set) return;
+    if (g_tune.lanes_per_walker) c->lanes_per_walker = (int)g_tune.lanes_per_walker;
+    if (g_tune.lds_tile) c->lds_tile = (int)g_tune.lds_tile;
+    if (g_tune.list_cap) c->list_cap = (int)g_tune.list_cap;
+    c->mode = (int)g_tune.route;
+  }
+  if (c->lanes_per_walker < 16) c->lanes_per_walker = 16;  // the queue kernel's smallest group
+  const size_t gpb = 256 / (size_t)c->lanes_per_walker;
+  auto bytes = [&]() { return gpb * (2 * (size_t)c->lds_tile + 2 * (size_t)c->list_cap) * 4; };
+  while (bytes() > di.lds_per_block_max && (c->lds_tile > 1 || c->list_cap > 1)) {
+    if (c->lds_tile >= c->list_cap && c->lds_tile > 1) c->lds_tile /= 2;
+    else c->list_cap /= 2;
+  }
+  c->grid_blocks = 0;
+}
+
 bool generic_only() {
   std::lock_guard<std::mutex> lk(g_mu);
   return g_tune_set && (g_tune.flags & N2V_TUNE_GENERIC_ONLY);
@@ -157,6 +176,9 @@ int prepare_request(const GraphRec& gr, uint32_t kind, const int32_t* d_starts, 
     a->second_order = 0;
   } else if (Q16 == kC16Host) *path = Path::kReturnOnly;
   else *path = Path::kGeneric;
+  a->path = (uint32_t)*path;
+  a->pad = 0;
+  a->steps = nullptr;
   return N2V_OK;
 }
 

@@ -18,6 +18,13 @@ struct GraphDev {
   uint64_t m = 0;
 };
 
+// Which kernel family serves a request.
+enum class Path : int {
+  kFirstOrder = 0,  // lane per walker: unweighted multiply-shift / weighted prefix search
+  kReturnOnly = 1,  // node2vec with Q16 == 65536: lane per walker, O(log d) per step
+  kGeneric = 2      // node2vec with Q16 != 65536: G lanes per walker
+};
+
 // One walk request as the kernels see it.
 struct WalkArgs {
   GraphDev g;
@@ -31,13 +38,16 @@ struct WalkArgs {
   uint64_t wid_base;
   int32_t* Y;
   int32_t* lens;
+  uint32_t path;  // Path, used by the batched kernel
+  uint32_t pad;
+  unsigned long long* steps;  // if non-null: += sum over walks of (len - 1)
 };
 
-// Which kernel family serves a request.
-enum class Path : int {
-  kFirstOrder = 0,  // lane per walker: unweighted multiply-shift / weighted prefix search
-  kReturnOnly = 1,  // node2vec with Q16 == 65536: lane per walker, O(log d) per step
-  kGeneric = 2      // node2vec with Q16 != 65536: G lanes per walker
+// A slice [w0, w1) of the walk rows of request `req`, for the batched kernel.
+struct QueueChunk {
+  uint32_t req;
+  uint32_t pad;
+  uint64_t w0, w1;
 };
 
 struct LaunchCfg {
@@ -57,6 +67,12 @@ struct DevInfo {
 
 hipError_t launch_walks(const WalkArgs& a, Path path, const LaunchCfg& cfg, const DevInfo& di,
                         hipStream_t st);
+// Grid of the persistent batched kernel for this shape.
+int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks);
+// Persistent batched launch: resets *d_head (device) with a kernel, then the
+// queue kernel drains d_chunks.  Graph-capturable (no memset nodes).
+hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint32_t nchunks,
+                        uint32_t* d_head, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st);
 
 // Graph preparation.  stats: [0] error flags, [1] max degree, [2] max row sum,
 // [3] sum of degree^2 (device uint64[4], zeroed by the caller).

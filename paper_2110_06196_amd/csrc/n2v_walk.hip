@@ -47,14 +47,14 @@ namespace {
 
 enum { kFoUnw = 0, kFoW = 1, kRetUnw = 2, kRetW = 3 };
 
+// One whole walk (row w of request a) by one lane.
 template <int MODE, typename RT>
-__global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a) {
+__device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const uint32_t* __restrict__ W = a.g.W;
   const RT* __restrict__ R = (const RT*)a.g.R;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwalks; w += stride) {
+  {
     int32_t* __restrict__ row = a.Y + w * a.L;
     const int32_t start = a.starts[w % a.ns];
     const uint64_t wid = a.wid_base + w;
@@ -104,7 +104,15 @@ __global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a) {
     }
     for (uint32_t s = len; s < a.L; ++s) row[s] = -1;
     if (a.lens) a.lens[w] = (int32_t)len;
+    if (a.steps && len > 1) atomicAdd(a.steps, (unsigned long long)(len - 1));
   }
+}
+
+template <int MODE, typename RT>
+__global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwalks; w += stride)
+    lane_walk<MODE, RT>(a, w);
 }
 
 __device__ __forceinline__ bool lds_contains(const int32_t* A, uint32_t n, int32_t x) {
@@ -163,19 +171,21 @@ __device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl,
 // G / nk lanes assigned to one key probe k evenly spaced points per round, so
 // a search takes about log_{k+1}(n) dependent loads instead of log2(n).
 // Returns, in lane l < nk, whether its key is in A and (if so) its index.
+// LDS words per walker group: two staging tiles and the list (positions, weights).
+__host__ __device__ constexpr int group_lds_words(int tile, int cap) { return 2 * tile + 2 * cap; }
+
+// One whole walk (row w of request a) by one group of G lanes; mem is the
+// group's LDS region of group_lds_words(tile, cap) words.
 template <int G, bool WEIGHTED, typename RT>
-__global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
-  extern __shared__ int32_t lds[];
+__device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
+                                           int mode_knob) {
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);
-  const int gib = threadIdx.x / G;
-  const int gpb = blockDim.x / G;
-  int32_t* const bufA = lds + (size_t)gib * (2 * tile + 2 * cap);
+  int32_t* const bufA = mem;
   int32_t* const bufB = bufA + tile;
   uint32_t* const lpos = (uint32_t*)(bufB + tile);
   uint32_t* const lw = lpos + cap;
-  const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const uint32_t* __restrict__ W = a.g.W;
@@ -185,7 +195,7 @@ __global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap,
   const uint64_t cdel = (uint64_t)kC16 - Q16;  // common minus far, mod 2^64
   const uint64_t rdel = P16 - Q16;             // return minus far, mod 2^64
 
-  for (uint64_t w = (uint64_t)blockIdx.x * gpb + gib; w < a.nwalks; w += ngroups) {
+  {
     int32_t* __restrict__ row = a.Y + w * a.L;
     const int32_t start = a.starts[w % a.ns];
     const uint64_t wid = a.wid_base + w;
@@ -444,8 +454,70 @@ __global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap,
       if (idx < a.L) row[idx] = (s == s0 && idx < len) ? ob : -1;
     }
     if (a.lens && gl == 0) a.lens[w] = (int32_t)len;
+    if (a.steps && gl == 0 && len > 1) atomicAdd(a.steps, (unsigned long long)(len - 1));
   }
 }
+
+template <int G, bool WEIGHTED, typename RT>
+__global__ __launch_bounds__(256) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
+  extern __shared__ int32_t lds[];
+  const int gib = threadIdx.x / G;
+  const int gpb = blockDim.x / G;
+  int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap);
+  const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
+  for (uint64_t w = (uint64_t)blockIdx.x * gpb + gib; w < a.nwalks; w += ngroups)
+    group_walk<G, WEIGHTED, RT>(a, w, mem, tile, cap, mode_knob);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched kernel: groups pop walk chunks (request, first row, end
+// row) from a device queue ordered longest-estimated-first and run each walk
+// with the same per-walk routines as the plain kernels.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ void lane_dispatch(const WalkArgs& a, uint64_t w) {
+  const bool weighted = a.g.W != nullptr;
+  const bool r64 = a.g.r_bytes == 8;
+  if (a.path == (uint32_t)Path::kFirstOrder) {
+    if (!weighted) lane_walk<kFoUnw, uint32_t>(a, w);
+    else if (r64) lane_walk<kFoW, uint64_t>(a, w);
+    else lane_walk<kFoW, uint32_t>(a, w);
+  } else {
+    if (!weighted) lane_walk<kRetUnw, uint32_t>(a, w);
+    else if (r64) lane_walk<kRetW, uint64_t>(a, w);
+    else lane_walk<kRetW, uint32_t>(a, w);
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_walk_queue(const WalkArgs* __restrict__ reqs,
+                                                    const QueueChunk* __restrict__ chunks, uint32_t nchunks,
+                                                    uint32_t* __restrict__ head, int tile, int cap,
+                                                    int mode_knob) {
+  extern __shared__ int32_t lds[];
+  const int gl = (threadIdx.x & 63) & (G - 1);
+  const int gib = threadIdx.x / G;
+  int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap);
+  while (true) {
+    uint32_t c = 0;
+    if (gl == 0) c = atomicAdd(head, 1u);
+    c = (uint32_t)grp_bcast_i32<G>((int32_t)c, 0);
+    if (c >= nchunks) break;  // every group exits once the queue is drained
+    const QueueChunk ch = chunks[c];
+    const WalkArgs a = reqs[ch.req];
+    if (a.path != (uint32_t)Path::kGeneric) {
+      for (uint64_t w = ch.w0 + (uint64_t)gl; w < ch.w1; w += G) lane_dispatch<G>(a, w);
+    } else if (a.g.W == nullptr) {
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, false, uint32_t>(a, w, mem, tile, cap, mode_knob);
+    } else if (a.g.r_bytes == 8) {
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint64_t>(a, w, mem, tile, cap, mode_knob);
+    } else {
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint32_t>(a, w, mem, tile, cap, mode_knob);
+    }
+  }
+}
+
+__global__ void k_reset_counter(uint32_t* head) { *head = 0u; }
 
 // Grid size: enough blocks to fill every CU at the kernel's occupancy, never
 // more than the work needs (the kernels loop over walkers).
@@ -484,7 +556,7 @@ template <int G, bool WEIGHTED, typename RT>
 hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   auto k = k_walk_n2v<G, WEIGHTED, RT>;
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * (2 * (size_t)cfg.lds_tile + 2 * (size_t)cfg.list_cap) * sizeof(int32_t);
+  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cfg.mode);
   return hipGetLastError();
@@ -501,7 +573,40 @@ hipError_t go_n2v_g(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, 
   }
 }
 
+template <int G>
+hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nchunks, uint32_t* head,
+                    const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
+  auto k = k_walk_queue<G>;
+  const int gpb = 256 / G;
+  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap) * sizeof(int32_t);
+  int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, ((uint64_t)nchunks + gpb - 1) / gpb, di);
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, head);
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, reqs, chunks, nchunks, head, cfg.lds_tile,
+                     cfg.list_cap, cfg.mode);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks) {
+  const int G = cfg.lanes_per_walker == 16 ? 16 : (cfg.lanes_per_walker == 32 ? 32 : 64);
+  const int gpb = 256 / G;
+  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap) * sizeof(int32_t);
+  const uint64_t work = ((uint64_t)nchunks + gpb - 1) / gpb;
+  if (G == 16) return grid_for(k_walk_queue<16>, lds, work, di);
+  if (G == 32) return grid_for(k_walk_queue<32>, lds, work, di);
+  return grid_for(k_walk_queue<64>, lds, work, di);
+}
+
+hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint32_t nchunks,
+                        uint32_t* d_head, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
+  if (nchunks == 0) return hipSuccess;
+  switch (cfg.lanes_per_walker) {
+    case 16: return go_queue<16>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
+    case 32: return go_queue<32>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
+    default: return go_queue<64>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
+  }
+}
 
 hipError_t launch_walks(const WalkArgs& a, Path path, const LaunchCfg& cfg, const DevInfo& di,
                         hipStream_t st) {
