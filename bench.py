@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--runs", default="1,1;0.25,4", help="(p,q) pairs, ';'-separated")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--walk-len", type=int, default=100)
+    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served"],
+                    help="chung_lu_1m: plain launches (default); batched: 64 graphs x 4096 requests, one "
+                         "launch per request vs one persistent hipGraph launch; served: the same requests "
+                         "under Poisson arrivals, server vs one launch per request")
+    ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (req/s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (PMC counter calibration)")
     ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
@@ -231,6 +236,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.config == "batched":
+        bench_batched(args)
+        return
+    if args.config == "served":
+        bench_served(args)
+        return
     import torch
     import paper_2110_06196_amd as n2v
 
@@ -361,6 +372,271 @@ def main():
     }
     print(json.dumps(out), flush=True)
     n2v.n2v_graph_release(g)
+
+
+# ---------------------------------------------------------------------------
+# Many graphs, many requests
+# ---------------------------------------------------------------------------
+def _gen(params):
+    import synth
+    return synth.many_graph(params)
+
+
+def many_graphs_on_device(torch, n2v, dev):
+    import multiprocessing as mp
+    import synth
+    ps = synth.many_graph_params()
+    t0 = time.time()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        host = pool.map(_gen, ps, chunksize=1)
+    print(f"[bench] 64 graphs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    graphs = []
+    for (O, D, W) in host:
+        Ot = torch.from_numpy(O.view(np.int64)).to(dev)
+        Dt = torch.from_numpy(D).to(dev)
+        Wt = torch.from_numpy(W.view(np.int32)).to(dev)
+        graphs.append((n2v.n2v_graph_upload(Ot, Dt, Wt), (Ot, Dt, Wt)))
+    return ps, host, graphs
+
+
+def _requests_on_device(torch, dev, reqs):
+    bufs = []
+    for r in reqs:
+        S = torch.from_numpy(r["starts"]).to(dev)
+        nw = r["starts"].size
+        bufs.append((S, torch.empty((nw, r["walk_len"]), dtype=torch.int32, device=dev),
+                     torch.empty(nw, dtype=torch.int32, device=dev)))
+    return bufs
+
+
+def _oracle_sample(host, reqs, per_req, threads, outs=None, torch=None):
+    """Oracle on `per_req` evenly spaced walks of every request; returns
+    (steps, seconds, mismatching rows vs outs)."""
+    import concurrent.futures as cf
+    import oracle
+    jobs = []
+    for k, r in enumerate(reqs):
+        nw = r["starts"].size
+        rows = np.unique(np.linspace(0, nw - 1, min(per_req, nw)).astype(np.int64))
+        jobs.append((k, rows))
+
+    def one(job):
+        k, rows = job
+        r = reqs[k]
+        O, D, W = host[r["graph"]]
+        return k, rows, oracle.walks(O, D, W, r["starts"], 1, r["walk_len"], oracle.NODE2VEC, r["p"], r["q"],
+                                     r["seed"], 0, rows)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, jobs))
+    dt = time.perf_counter() - t0
+    steps = sum(int(np.maximum(lo.astype(np.int64) - 1, 0).sum()) for _, _, (_, lo) in res)
+    mism = 0
+    if outs is not None:
+        for k, rows, (Yo, lo) in res:
+            idx = torch.from_numpy(rows).to(outs[k][1].device)
+            Yg = outs[k][1].index_select(0, idx).cpu().numpy()
+            lg = outs[k][2].index_select(0, idx).cpu().numpy()
+            mism += int(((Yg != Yo).any(axis=1) | (lg != lo)).sum())
+    return steps, dt, mism
+
+
+def bench_batched(args):
+    import torch
+    import paper_2110_06196_amd as n2v
+    import synth
+    dev = torch.device("cuda:0")
+    ps, host, graphs = many_graphs_on_device(torch, n2v, dev)
+    reqs = synth.many_requests([p["n"] for p in ps])
+    plain_out = _requests_on_device(torch, dev, reqs)
+    batch_out = _requests_on_device(torch, dev, reqs)
+    stream = torch.cuda.current_stream()
+
+    def plain_pass():
+        for r, (S, Y, lens) in zip(reqs, plain_out):
+            n2v.n2v_walks_node2vec(graphs[r["graph"]][0], S, 1, r["walk_len"], r["p"], r["q"], r["seed"], 0,
+                                   Y, lens, stream=stream)
+
+    descs = [n2v.make_request(graphs[r["graph"]][0], n2v.N2V_NODE2VEC, S, 1, r["walk_len"], r["p"], r["q"],
+                              r["seed"], 0, Y, lens) for r, (S, Y, lens) in zip(reqs, batch_out)]
+    for _ in range(args.warmup):
+        plain_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_pass()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] plain pass {t_plain:.3f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plan = n2v.n2v_batch_create(descs, autotune=True)
+    t_create = time.perf_counter() - t0
+    info = n2v.n2v_batch_info(plan)
+    for _ in range(args.warmup):
+        n2v.n2v_batch_launch(plan, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        n2v.n2v_batch_launch(plan, stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    print(f"[bench] batched pass {t_batched:.3f}s (create {t_create:.2f}s)", file=sys.stderr, flush=True)
+    steps = sum(int((lens.to(torch.int64) - 1).clamp(min=0).sum().item()) for _, _, lens in batch_out)
+    same = sum(int(not (torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]))) for a, b in zip(plain_out, batch_out))
+    cpu = None
+    parity = {"requests_differing_from_plain": same}
+    if args.cpu_seconds > 0:
+        threads = min(16, os.cpu_count() or 1)
+        csteps, ct, mism = _oracle_sample(host, reqs, 4, threads, batch_out, torch)
+        cpu = {"value": csteps / ct, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"4 evenly spaced walks of each of the {len(reqs)} requests ({csteps} steps, {ct:.1f} s)"}
+        parity["oracle_sample_mismatching_rows"] = mism
+    out = {
+        "metric": METRIC, "value": steps / t_batched, "unit": "walk steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_batched * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batched: 64 Chung-Lu graphs (n log-uniform 1e3..1e6, mean degree U[8,32], "
+                               "gamma 2.2, weights U[1,100]); 4096 node2vec requests (1..1e4 starts, length "
+                               "U[10,200], (p,q) in {0.25,1,4}^2)",
+                   "form": "batched: one persistent hipGraph-captured launch",
+                   "n_requests": len(reqs), "n_walks": int(info["n_walks"]), "chunks": int(info["n_chunks"]),
+                   "autotuned_shape": [int(info["lanes_per_walker"]), int(info["lds_tile"]), int(info["list_cap"])]},
+        "plain": {"value": steps / t_plain, "ms_per_step": t_plain * 1e3, "form": "one launch per request"},
+        "speedup_vs_plain": t_plain / t_batched,
+        "batched_kernel_ms": k_ms, "plan_create_s": t_create,
+        "cpu_baseline": cpu, "parity_sample": parity, "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+    n2v.n2v_batch_destroy(plan)
+
+
+def bench_served(args):
+    import threading
+    import torch
+    import paper_2110_06196_amd as n2v
+    import synth
+    dev = torch.device("cuda:0")
+    ps, host, graphs = many_graphs_on_device(torch, n2v, dev)
+    reqs = synth.many_requests([p["n"] for p in ps])
+    outs = _requests_on_device(torch, dev, reqs)
+    stream = torch.cuda.current_stream()
+    hdesc = [n2v.host_request(graphs[r["graph"]][0], n2v.N2V_NODE2VEC, r["starts"], 1, r["walk_len"], r["p"],
+                              r["q"], r["seed"])[0] for r in reqs]
+    skip = len(reqs) // 20  # the first 5% of arrivals are warm-up
+
+    def pct(lat):
+        lat = np.sort(np.asarray(lat[skip:], dtype=np.float64)) / 1e6
+        return float(lat[int(0.5 * (lat.size - 1))]), float(lat[int(np.ceil(0.99 * (lat.size - 1)))])
+
+    def wait_until(t_ns):
+        while True:
+            d = t_ns - time.monotonic_ns()
+            if d <= 0:
+                return
+            if d > 2_000_000:
+                time.sleep((d - 1_000_000) / 1e9)
+
+    results = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        arr = synth.poisson_arrivals(len(reqs), rate)
+        # --- server: continuous batching
+        srv = n2v.n2v_server_create(200 << 30, 4096)
+        for g, _ in graphs:
+            n2v.n2v_server_add_graph(srv, g)
+        ids = [0] * len(reqs)
+        lat = [0] * len(reqs)
+        steps = [0] * len(reqs)
+        done_t = [0] * len(reqs)
+        submitted = [0]
+        t0 = time.monotonic_ns() + 20_000_000
+
+        def poller():
+            pending = set()
+            seen = 0
+            left = len(reqs)
+            while left:
+                upto = submitted[0]
+                pending.update(range(seen, upto))
+                seen = upto
+                for k in list(pending):
+                    res = n2v.n2v_request_poll(srv, ids[k])
+                    if res is not None:
+                        lat[k] = res.t_done_ns - res.t_arrival_ns
+                        done_t[k] = res.t_done_ns
+                        steps[k] = res.steps
+                        n2v.n2v_request_release(srv, ids[k])
+                        pending.discard(k)
+                        left -= 1
+                time.sleep(0.0002)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        for k in range(len(reqs)):
+            ta = t0 + int(arr[k] * 1e9)
+            wait_until(ta)
+            ids[k] = n2v.n2v_request_submit(srv, hdesc[k], ta)
+            submitted[0] = k + 1
+        th.join()
+        n2v.n2v_server_destroy(srv)
+        s50, s99 = pct(lat)
+        s_tput = sum(steps) / ((max(done_t) - t0) / 1e9)
+        print(f"[bench] served rate {rate:g}: p50 {s50:.1f} ms p99 {s99:.1f} ms", file=sys.stderr, flush=True)
+        # --- baseline: one plain launch per request, FIFO, one stream
+        events = [None] * len(reqs)
+        blat = [0] * len(reqs)
+        bdone = [0] * len(reqs)
+        launched = [0]
+        t0 = time.monotonic_ns() + 20_000_000
+
+        def bpoller():
+            k = 0
+            while k < len(reqs):
+                if k >= launched[0]:
+                    time.sleep(0.0001)
+                    continue
+                if events[k].query():
+                    now = time.monotonic_ns()
+                    bdone[k] = now
+                    blat[k] = now - (t0 + int(arr[k] * 1e9))
+                    k += 1
+                else:
+                    time.sleep(0.00005)
+
+        th = threading.Thread(target=bpoller)
+        th.start()
+        for k, (r, (S, Y, lens)) in enumerate(zip(reqs, outs)):
+            wait_until(t0 + int(arr[k] * 1e9))
+            n2v.n2v_walks_node2vec(graphs[r["graph"]][0], S, 1, r["walk_len"], r["p"], r["q"], r["seed"], 0, Y, lens,
+                                   stream=stream)
+            e = torch.cuda.Event()
+            e.record(stream)
+            events[k] = e
+            launched[0] = k + 1
+        th.join()
+        b50, b99 = pct(blat)
+        bsteps = sum(int((l.to(torch.int64) - 1).clamp(min=0).sum().item()) for _, _, l in outs)
+        b_tput = bsteps / ((max(bdone) - t0) / 1e9)
+        print(f"[bench] plain rate {rate:g}: p50 {b50:.1f} ms p99 {b99:.1f} ms", file=sys.stderr, flush=True)
+        results.append({"rate_rps": rate, "served": {"steps_per_s": s_tput, "p50_ms": s50, "p99_ms": s99},
+                        "one_launch_per_request": {"steps_per_s": b_tput, "p50_ms": b50, "p99_ms": b99},
+                        "steps": int(sum(steps)), "steps_match": int(sum(steps)) == bsteps})
+    top = results[-1]
+    out = {
+        "metric": METRIC, "value": top["served"]["steps_per_s"], "unit": "walk steps/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": skip, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "served: same 64 graphs and 4096 requests as the batched workload, open-loop "
+                               "Poisson arrivals (seed 11), budget 200 GB, latency = done - scheduled arrival, "
+                               "first 5% excluded", "form": "served (continuous batching)",
+                   "value_at_rate_rps": top["rate_rps"]},
+        "rates": results, "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -279,3 +279,46 @@ def chung_lu_1m():
     """1M nodes, 10M undirected edge samples, degree exponent 2.2, mean degree 20,
     max expected degree 5e4, weights uniform in [1, 100], seed 2."""
     return chung_lu(1_000_000, 10_000_000, 2.2, 20.0, 5.0e4, (1, 100), seed=2)
+
+
+# --------------------------------------------------------------------------
+# Many-graph, many-request workloads (batched and served forms)
+# --------------------------------------------------------------------------
+def many_graph_params(n_graphs: int = 64):
+    """Graph g: n log-uniform in [1e3, 1e6], mean degree uniform in [8, 32],
+    degree exponent 2.2, max expected degree sqrt(n * mean), weights U[1, 100],
+    seed 100 + g."""
+    out = []
+    for g in range(n_graphs):
+        rng = np.random.default_rng(100 + g)
+        n = int(round(math.exp(rng.uniform(math.log(1e3), math.log(1e6)))))
+        dbar = float(rng.uniform(8.0, 32.0))
+        out.append(dict(n=n, n_edges=int(n * dbar / 2), mean_deg=dbar, w_max=math.sqrt(n * dbar), seed=100 + g))
+    return out
+
+
+def many_graph(params: dict):
+    return chung_lu(params["n"], params["n_edges"], 2.2, params["mean_deg"], params["w_max"], (1, 100),
+                    seed=params["seed"])
+
+
+def many_requests(graph_nodes, n_requests: int = 4096, seed: int = 7, max_starts: int = 10_000):
+    """Request k: graph uniform, 1..max_starts start nodes drawn uniformly with
+    replacement, walk length uniform in [10, 200], (p, q) uniform over
+    {0.25, 1, 4}^2, one walk per start, Philox seed 1000 + k."""
+    rng = np.random.default_rng(seed)
+    grid = [0.25, 1.0, 4.0]
+    reqs = []
+    for k in range(n_requests):
+        g = int(rng.integers(0, len(graph_nodes)))
+        ns = int(rng.integers(1, max_starts + 1))
+        starts = rng.integers(0, graph_nodes[g], size=ns).astype(np.int32)
+        reqs.append(dict(graph=g, starts=starts, walk_len=int(rng.integers(10, 201)),
+                         p=grid[int(rng.integers(0, 3))], q=grid[int(rng.integers(0, 3))], seed=1000 + k))
+    return reqs
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 11) -> np.ndarray:
+    """Open-loop arrival times (seconds from 0) of a Poisson process."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
