@@ -39,34 +39,79 @@ __device__ __forceinline__ uint64_t scale_draw(uint64_t r, uint64_t total) {
 }
 
 // ---------------------------------------------------------------------------
+// Whole-wavefront collectives on DPP (data-parallel primitives) and readlane,
+// which stay in the vector ALU instead of the LDS permute pipe.  All 64 lanes
+// must be active.
+// ---------------------------------------------------------------------------
+// Inclusive 64-lane scan of 32-bit values: row_shr 1, 2, 4, 8 scan each row of
+// 16 lanes; row_bcast 15 and 31 then carry row totals into the later rows.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+// Exact 64-bit scan: three limbs of at most 22 bits, so every 64-lane partial
+// sum of a limb fits in 32 bits; recombined modulo 2^64.
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+  const uint32_t a = wave_incl_scan_u32((uint32_t)(x & 0x3FFFFFull));
+  const uint32_t b = wave_incl_scan_u32((uint32_t)((x >> 22) & 0x3FFFFFull));
+  const uint32_t c = wave_incl_scan_u32((uint32_t)(x >> 44));
+  return (uint64_t)a + ((uint64_t)b << 22) + ((uint64_t)c << 44);
+}
+
+__device__ __forceinline__ uint64_t wave_read_u64(uint64_t x, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// ---------------------------------------------------------------------------
 // Sub-wave groups of G lanes (G divides 64).  Control flow is uniform inside
-// a group, so the cross-lane reads below only touch active lanes.
+// a group, so the cross-lane reads below only touch active lanes.  A group of
+// 64 is the whole wavefront and uses the DPP / readlane forms.
 // ---------------------------------------------------------------------------
 template <int G>
 __device__ __forceinline__ uint64_t grp_sum(uint64_t x) {
+  if constexpr (G == 64) {
+    return wave_read_u64(wave_incl_scan_u64(x), 63);
+  } else {
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
-  return x;
+    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+    return x;
+  }
 }
 
 template <int G>
 __device__ __forceinline__ uint64_t grp_incl_scan(uint64_t x, int gl) {
+  if constexpr (G == 64) {
+    (void)gl;
+    return wave_incl_scan_u64(x);
+  } else {
 #pragma unroll
-  for (int o = 1; o < G; o <<= 1) {
-    uint64_t y = __shfl_up(x, (unsigned)o, G);
-    if (gl >= o) x += y;
+    for (int o = 1; o < G; o <<= 1) {
+      uint64_t y = __shfl_up(x, (unsigned)o, G);
+      if (gl >= o) x += y;
+    }
+    return x;
   }
-  return x;
 }
 
+// src is the same for every lane of the group.
 template <int G>
 __device__ __forceinline__ uint64_t grp_bcast(uint64_t x, int src) {
-  return __shfl(x, src, G);
+  if constexpr (G == 64) return wave_read_u64(x, src);
+  else return __shfl(x, src, G);
 }
 
 template <int G>
 __device__ __forceinline__ int32_t grp_bcast_i32(int32_t x, int src) {
-  return __shfl(x, src, G);
+  if constexpr (G == 64) return __builtin_amdgcn_readlane(x, src);
+  else return __shfl(x, src, G);
 }
 
 // Mask of the lanes of this group (bit i = group lane i) whose pred is true.

@@ -140,9 +140,9 @@ int upload_tables(const std::vector<Prepared>& reqs, const std::vector<QueueChun
 }
 
 double chunk_target(double total, const DevInfo& di) {
-  // about eight chunks per resident walker group of a 64-lane launch
+  // about 32 chunks per resident walker group of a 64-lane launch
   const double groups = (double)(di.cus > 0 ? di.cus : 256) * 16.0;
-  return std::max(total / (groups * 8.0), 1.0);
+  return std::max(total / (groups * 32.0), 1.0);
 }
 
 LaunchCfg batch_default_cfg(const DevInfo& di) {
@@ -295,8 +295,7 @@ struct Server {
   LaunchCfg cfg;
   DevInfo di;
   int device = 0;
-  double units_per_us = 2000.0;  // learned from completed quanta
-  double quantum_us = 2000.0;
+  size_t quantum_chunks = 0;  // chunks per quantum: twice the resident walker groups
   int fatal = N2V_OK;
 };
 
@@ -351,11 +350,9 @@ void admit_locked(Server* s) {
     }
     r->args.steps = s->d_steps + r->slot;
     r->walk_cost = (double)(d.walk_len > 1 ? d.walk_len - 1 : 1) * step_cost(*r->gr, path);
-    // chunks of about 1/8 of a quantum, whole multiples of 64 rows on lane paths
-    const double target = std::max(1.0, s->units_per_us * s->quantum_us / 64.0);
-    uint64_t cw = (uint64_t)std::max(1.0, std::floor(target / std::max(r->walk_cost, 1e-9)));
-    if (path != Path::kGeneric) cw = std::max<uint64_t>(64, (cw + 63) / 64 * 64);
-    r->chunk_rows = cw;
+    // the finest grain each group shape can use: one walk on the node2vec
+    // path (a whole group per walk), one wave of walks on the lane paths
+    r->chunk_rows = path == Path::kGeneric ? 1 : 64;
     r->state = RState::kActive;
     s->active.push_back(r);
   }
@@ -363,13 +360,14 @@ void admit_locked(Server* s) {
 
 // Build the next quantum's chunk list (under mu): one chunk for every active
 // request with rows left (so every admitted request progresses), then more
-// chunks oldest-first until the quantum's estimated work is reached.
+// chunks oldest-first until the quantum holds enough chunks to keep every
+// resident walker group busy for a couple of walks.
 void build_quantum_locked(Server* s, Quantum* q, std::vector<WalkArgs>* reqs, std::vector<QueueChunk>* chunks) {
   q->rows.clear();
   q->est = 0;
   reqs->clear();
   chunks->clear();
-  const double budget = s->units_per_us * s->quantum_us;
+  const size_t budget = s->quantum_chunks;
   std::unordered_map<SrvReq*, uint32_t> idx;
   auto take = [&](SrvReq* r) {
     const uint64_t w0 = r->next_row, w1 = std::min(r->nwalks, w0 + r->chunk_rows);
@@ -389,9 +387,9 @@ void build_quantum_locked(Server* s, Quantum* q, std::vector<WalkArgs>* reqs, st
     r->next_row = w1;
   };
   for (SrvReq* r : s->active)
-    if (r->next_row < r->nwalks) take(r);
+    if (r->next_row < r->nwalks && chunks->size() < budget) take(r);
   for (SrvReq* r : s->active)
-    while (r->next_row < r->nwalks && q->est < budget) take(r);
+    while (r->next_row < r->nwalks && chunks->size() < budget) take(r);
 }
 
 int launch_quantum(Server* s, Quantum* q, const std::vector<WalkArgs>& reqs, const std::vector<QueueChunk>& chunks) {
@@ -429,7 +427,6 @@ void dispatcher(Server* s) {
   std::vector<WalkArgs> reqs;
   std::vector<QueueChunk> chunks;
   int next_q = 0;
-  uint64_t last_done = 0;
   while (true) {
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->fatal != N2V_OK && inflight.empty()) {
@@ -479,15 +476,7 @@ void dispatcher(Server* s) {
       lk.lock();
       inflight.pop_front();
       q->busy = false;
-      if (e != hipSuccess) {
-        s->fatal = N2V_ERR_HIP;
-      } else {
-        // learn the work rate from the time this quantum had the GPU to itself
-        const uint64_t began = std::max(q->t_launch, last_done);
-        const double us = (double)(t - began) / 1000.0;
-        if (us > 50.0 && q->est > 0) s->units_per_us = 0.8 * s->units_per_us + 0.2 * (q->est / us);
-      }
-      last_done = t;
+      if (e != hipSuccess) s->fatal = N2V_ERR_HIP;
       for (auto& pr : q->rows) {
         SrvReq* r = pr.first;
         r->rows_done += pr.second;
@@ -687,7 +676,8 @@ int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, void* reser
     delete s;
     return hip_fail(e, "server create");
   }
-  s->cfg.grid_blocks = 0;
+  s->cfg.grid_blocks = queue_grid_blocks(s->cfg, s->di, 1u << 30);
+  s->quantum_chunks = (size_t)s->cfg.grid_blocks * (256 / (size_t)s->cfg.lanes_per_walker) * 2;
   s->th = std::thread(dispatcher, s);
   std::lock_guard<std::mutex> lk(g_srv_mu);
   s->handle = g_next_srv++;
