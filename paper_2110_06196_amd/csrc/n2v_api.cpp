@@ -88,8 +88,11 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
   LaunchCfg c;
   const double ed = gr.n_entries ? (double)gr.sum_deg_sq / (double)gr.n_entries : 0.0;
   c.lanes_per_walker = ed > 256 ? 64 : (ed > 48 ? 32 : 16);
-  c.lds_tile = c.lanes_per_walker == 64 ? 512 : (c.lanes_per_walker == 32 ? 512 : 256);
-  c.list_cap = c.lanes_per_walker == 64 ? 256 : (c.lanes_per_walker == 32 ? 256 : 128);
+  // LDS per group: a short staging tile and a long common-neighbour list (a
+  // list overflow costs a two-pass stream of the row; a miss in the tile only
+  // a bisection in global memory); 8 blocks of 256 threads fit one CU.
+  c.lds_tile = c.lanes_per_walker == 64 ? 64 : (c.lanes_per_walker == 32 ? 64 : 32);
+  c.list_cap = c.lanes_per_walker == 64 ? 576 : (c.lanes_per_walker == 32 ? 256 : 128);
   c.mode = 0;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_tune_set) {

@@ -148,8 +148,8 @@ double chunk_target(double total, const DevInfo& di) {
 LaunchCfg batch_default_cfg(const DevInfo& di) {
   LaunchCfg c;
   c.lanes_per_walker = 64;
-  c.lds_tile = 512;
-  c.list_cap = 256;
+  c.lds_tile = 64;
+  c.list_cap = 576;
   (void)di;
   return c;
 }
@@ -202,7 +202,7 @@ int autotune(BatchPlan* p) {
   (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  const int shapes[][3] = {{64, 512, 256}, {64, 256, 128}, {32, 256, 128}, {16, 128, 64}};
+  const int shapes[][3] = {{64, 64, 576}, {64, 128, 512}, {32, 64, 256}, {16, 32, 128}};
   float best = 1e30f;
   LaunchCfg best_cfg = p->cfg;
   hipError_t e = hipSuccess;
