@@ -295,7 +295,7 @@ struct Server {
   LaunchCfg cfg;
   DevInfo di;
   int device = 0;
-  size_t quantum_chunks = 0;  // chunks per quantum: twice the resident walker groups
+  size_t quantum_chunks = 0;  // chunks per quantum: eight per resident walker group
   int fatal = N2V_OK;
 };
 
@@ -360,8 +360,8 @@ void admit_locked(Server* s) {
 
 // Build the next quantum's chunk list (under mu): one chunk for every active
 // request with rows left (so every admitted request progresses), then more
-// chunks oldest-first until the quantum holds enough chunks to keep every
-// resident walker group busy for a couple of walks.
+// chunks oldest-first until the quantum holds about eight chunks for every
+// resident walker group.
 void build_quantum_locked(Server* s, Quantum* q, std::vector<WalkArgs>* reqs, std::vector<QueueChunk>* chunks) {
   q->rows.clear();
   q->est = 0;
@@ -390,6 +390,12 @@ void build_quantum_locked(Server* s, Quantum* q, std::vector<WalkArgs>* reqs, st
     if (r->next_row < r->nwalks && chunks->size() < budget) take(r);
   for (SrvReq* r : s->active)
     while (r->next_row < r->nwalks && chunks->size() < budget) take(r);
+  // longest estimated chunks first, so the quantum's tail is short walks
+  std::vector<double> cost(reqs->size());
+  for (auto& kv : idx) cost[kv.second] = kv.first->walk_cost;
+  std::stable_sort(chunks->begin(), chunks->end(), [&](const QueueChunk& a, const QueueChunk& b) {
+    return cost[a.req] * (double)(a.w1 - a.w0) > cost[b.req] * (double)(b.w1 - b.w0);
+  });
 }
 
 int launch_quantum(Server* s, Quantum* q, const std::vector<WalkArgs>& reqs, const std::vector<QueueChunk>& chunks) {
@@ -677,7 +683,7 @@ int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, void* reser
     return hip_fail(e, "server create");
   }
   s->cfg.grid_blocks = queue_grid_blocks(s->cfg, s->di, 1u << 30);
-  s->quantum_chunks = (size_t)s->cfg.grid_blocks * (256 / (size_t)s->cfg.lanes_per_walker) * 2;
+  s->quantum_chunks = (size_t)s->cfg.grid_blocks * (256 / (size_t)s->cfg.lanes_per_walker) * 8;
   s->th = std::thread(dispatcher, s);
   std::lock_guard<std::mutex> lk(g_srv_mu);
   s->handle = g_next_srv++;
