@@ -53,8 +53,9 @@ def parse():
     ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (req/s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (PMC counter calibration)")
-    ap.add_argument("--summarize-profiles", nargs=5, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
-                                                              "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+    ap.add_argument("--summarize-profiles", nargs=7, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
+                                                              "CAL_FETCH_DIR", "CAL_WRITE_DIR", "SQ_DIR",
+                                                              "TCC_DIR"),
                     help="write profiles/*.txt from rocprofv3 output directories and exit")
     return ap.parse_args()
 
@@ -124,6 +125,35 @@ def _pmc_per_kernel(d, counter):
     for (key, _), v in vals.items():
         per.setdefault(key, []).append(v)
     return {k: (sum(v) / len(v), len(v)) for k, v in per.items()}
+
+
+COUNTER_FILE = os.path.join(ROOT, "profiles", "pmc_counters_chung_lu_1m.txt")
+
+
+def summarize_counters(sq_dir, tcc_dir, cmds):
+    """Per-kernel SQ / TCC counters: instruction mix, wait share, L2 hit rate."""
+    names = ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+             "SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS"]
+    per = {n: _pmc_per_kernel(sq_dir, n) for n in names}
+    hit = _pmc_per_kernel(tcc_dir, "TCC_HIT_sum")
+    miss = _pmc_per_kernel(tcc_dir, "TCC_MISS_sum")
+    out = ["# rocprofv3 --pmc counters per dispatch (mean over dispatches), 1M-node Chung-Lu workload",
+           f"# sq command: {cmds['sq']}", f"# tcc command: {cmds['tcc']}", f"source_hash: {kernel_source_hash()}"]
+    for k in ("k_walk_n2v", "k_walk_lane"):
+        if k not in per["SQ_WAVES"]:
+            continue
+        v = {n: per[n].get(k, (0.0, 0))[0] for n in names}
+        waves = max(v["SQ_WAVES"], 1.0)
+        h, m = hit.get(k, (0.0, 0))[0], miss.get(k, (0.0, 0))[0]
+        out.append(f"{k} " + " ".join(f"{n}: {v[n]:.6e}" for n in names) +
+                   f" TCC_HIT_sum: {h:.6e} TCC_MISS_sum: {m:.6e}")
+        out.append(f"{k} valu_insts_per_wave: {v['SQ_INSTS_VALU'] / waves:.1f} "
+                   f"vmem_rd_insts_per_wave: {v['SQ_INSTS_VMEM_RD'] / waves:.1f} "
+                   f"lds_insts_per_wave: {v['SQ_INSTS_LDS'] / waves:.1f} "
+                   f"wait_any_share_of_wave_cycles: {v['SQ_WAIT_ANY'] / max(v['SQ_WAVE_CYCLES'], 1.0):.3f} "
+                   f"l2_hit_rate: {h / max(h + m, 1.0):.3f}")
+    open(COUNTER_FILE, "w").write("\n".join(out) + "\n")
+    print(open(COUNTER_FILE).read())
 
 
 def summarize_profiles(trace_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cmds):
@@ -225,9 +255,13 @@ def main():
             "python3 /root/repo/bench.py --steps 1 --warmup 0 --cpu-seconds 0"
         c = "cd /tmp && rocprofv3 --pmc {c} --output-format csv -d <dir> -o run -- " \
             "python3 /root/repo/bench.py --copy-calibration"
-        summarize_profiles(*args.summarize_profiles, cmds={
+        summarize_profiles(*args.summarize_profiles[:5], cmds={
             "trace": t, "fetch": f.format(c="FETCH_SIZE"), "write": f.format(c="WRITE_SIZE"),
             "cal_fetch": c.format(c="FETCH_SIZE"), "cal_write": c.format(c="WRITE_SIZE")})
+        summarize_counters(*args.summarize_profiles[5:], cmds={
+            "sq": f.format(c="SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_INSTS_VALU "
+                           "SQ_INSTS_VMEM_RD SQ_INSTS_LDS"),
+            "tcc": f.format(c="TCC_HIT_sum TCC_MISS_sum")})
         return
     if args.copy_calibration:
         copy_calibration()
