@@ -31,9 +31,12 @@
 //      and test each x against N(t) (kept in LDS when the previous row fit a
 //      ping-pong tile, else bisected in global memory).  The draw is then
 //      located by a ballot over B at the listed positions and a G-ary search
-//      of the segment between two of them.  If C overflows its LDS list the
-//      step streams the biased weights in two passes instead (block sums, then
-//      a scan of one block).
+//      of the segment between two of them.  C is kept in LDS one page at a
+//      time: the first pass counts every common neighbour (so the total is
+//      exact) and stores the first page; later pages are listed only if the
+//      draw lands beyond the stored ones.  A two-pass stream of the biased
+//      weights (block sums, then a scan of one block) remains as a route that
+//      can be forced for testing.
 #include "n2v_device.hpp"
 #include "n2v_internal.hpp"
 
@@ -307,92 +310,111 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           if (mode == kModeTwoPass) {
             two_pass();
           } else {
-            // Build the sorted list of positions j in N(v) whose candidate is a
-            // common neighbour (x in N(t), x != t), and the position of t.
-            uint32_t cnt = 0, pt = 0;
-            bool has_t = false;
+            // List the positions j in N(v) whose candidate is a common
+            // neighbour (x in N(t), x != t), in increasing j, one LDS page of
+            // `cap` entries at a time.  Every route visits keys in an order
+            // that makes the hit positions increase, so a page can be resumed
+            // from the key after its last stored hit.
+            uint32_t cnt = 0, pt = 0, stored = 0, resume = 0;
+            bool has_t = false, first = true;
             uint64_t acc = 0;
-            auto append = [&](bool hit, uint32_t pos) {
+            auto append = [&](bool hit, uint32_t pos, uint32_t key0) {
               const uint64_t m = grp_ballot<G>(hit, gbase);
+              if (m == 0) return;
               if (hit) {
-                const uint32_t idx = cnt + (uint32_t)__popcll(m & lt_mask);
+                const uint32_t idx = stored + (uint32_t)__popcll(m & lt_mask);
                 const uint32_t wv = WEIGHTED ? W[lo + pos] : 1u;
-                acc += wv;
+                if (first) acc += wv;
                 if (idx < (uint32_t)cap) {
                   lpos[idx] = pos;
                   lw[idx] = wv;
                 }
               }
-              cnt += (uint32_t)__popcll(m);
+              const uint32_t nh = (uint32_t)__popcll(m);
+              const uint32_t room = (uint32_t)cap - stored;
+              if (room > 0 && nh >= room) {
+                uint64_t mm = m;  // the room-th hit fills the page's last slot
+                for (uint32_t i = 1; i < room; ++i) mm &= mm - 1;
+                resume = key0 + (uint32_t)(__ffsll((unsigned long long)mm) - 1) + 1;
+              }
+              cnt += nh;
+              stored = min((uint32_t)cap, stored + nh);
             };
-            if (mode == kModeProbe) {
-              // keys: N(t) and, last, t itself (to find its position in N(v))
-              const uint32_t nk = td + 1;
-              for (uint32_t c = 0; c < nk; c += G) {
-                const uint32_t k = c + gl;
-                const bool act = k < nk;
-                const bool tkey = k == td;
-                int32_t y = t;
-                if (act && !tkey) y = t_in_lds ? cur[k] : D[tlo + k];
-                uint32_t pos = 0;
-                bool hit = false;
-                if (act) {
-                  pos = lower_bound_i32(D + lo, d, y);
-                  hit = pos < d && D[lo + pos] == y;
+            // keys [from, end): probe route keys are N(t) then t itself; stream
+            // route keys are the candidates of N(v).  Later pages stop once full.
+            auto gen = [&](uint32_t from) {
+              if (mode == kModeProbe) {
+                const uint32_t nk = td + 1;
+                for (uint32_t c = from; c < nk; c += G) {
+                  if (!first && stored >= (uint32_t)cap) break;
+                  const uint32_t k = c + gl;
+                  const bool act = k < nk;
+                  const bool tkey = k == td;
+                  int32_t y = t;
+                  if (act && !tkey) y = t_in_lds ? cur[k] : D[tlo + k];
+                  uint32_t pos = 0;
+                  bool hit = false;
+                  if (act) {
+                    pos = lower_bound_i32(D + lo, d, y);
+                    hit = pos < d && D[lo + pos] == y;
+                  }
+                  const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
+                  if (mt) {
+                    has_t = true;
+                    pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
+                  }
+                  // a self-loop at t puts t in N(t): that candidate is a return, not common
+                  append(hit && !tkey && y != t, pos, c);
                 }
-                const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
-                if (mt) {
-                  has_t = true;
-                  pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
+              } else {
+                const bool stg = first && d <= (uint32_t)tile;
+                for (uint32_t c = from; c < d; c += G) {
+                  if (!first && stored >= (uint32_t)cap) break;
+                  const uint32_t j = c + gl;
+                  const bool act = j < d;
+                  int32_t x = 0;
+                  if (act) {
+                    x = D[lo + j];
+                    if (stg) nxt[j] = x;
+                  }
+                  const bool isret = act && x == t;
+                  const uint64_t mt = grp_ballot<G>(isret, gbase);
+                  if (mt) {
+                    has_t = true;
+                    pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
+                  }
+                  bool in_t;
+                  if (t_in_lds) {
+                    in_t = act && !isret && lds_contains(cur, td, x);
+                  } else {
+                    in_t = act && !isret && global_contains(D + tlo, td, x);
+                  }
+                  append(act && !isret && in_t, j, c);
                 }
-                // a self-loop at t puts t in N(t): that candidate is a return, not common
-                append(hit && !tkey && y != t, pos);
+                if (first) staged = stg;
               }
-            } else {
-              const bool stg = d <= (uint32_t)tile;
-              for (uint32_t c = 0; c < d; c += G) {
-                const uint32_t j = c + gl;
-                const bool act = j < d;
-                int32_t x = 0;
-                if (act) {
-                  x = D[lo + j];
-                  if (stg) nxt[j] = x;
-                }
-                const bool isret = act && x == t;
-                const uint64_t mt = grp_ballot<G>(isret, gbase);
-                if (mt) {
-                  has_t = true;
-                  pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
-                }
-                bool in_t;
-                if (t_in_lds) {
-                  in_t = act && !isret && lds_contains(cur, td, x);
-                } else {
-                  in_t = act && !isret && global_contains(D + tlo, td, x);
-                }
-                append(act && !isret && in_t, j);
-              }
-              staged = stg;
-            }
-            // the list is read by other lanes of the group below
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (cnt > (uint32_t)cap) {
-              two_pass();  // list overflow: stream the biased weights instead
-            } else {
-              const uint64_t CW = grp_sum<G>(acc);
-              const uint64_t wt = has_t ? (WEIGHTED ? (uint64_t)W[lo + pt] : 1ull) : 0ull;
-              const uint64_t retw = rdel * wt;
-              const uint64_t total = Q16 * S + cdel * CW + retw;
-              if (total == 0) break;
-              const uint64_t T = scale_draw(r, total);
-              // B_j = Q16 R_j + cdel * (common weight up to j) + retw [j >= pt]
-              uint64_t E = 0, Eprev = CW;
-              uint32_t seg_lo = 0, seg_hi = d, lastpos = 0;
-              bool found = false;
-              for (uint32_t c = 0; c < cnt; c += G) {
+              // the page is read by other lanes of the group
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            };
+            gen(0);  // first pass: every hit counted, first page stored
+            first = false;
+            const uint64_t CW = grp_sum<G>(acc);
+            const uint64_t wt = has_t ? (WEIGHTED ? (uint64_t)W[lo + pt] : 1ull) : 0ull;
+            const uint64_t retw = rdel * wt;
+            const uint64_t total = Q16 * S + cdel * CW + retw;
+            if (total == 0) break;
+            const uint64_t T = scale_draw(r, total);
+            // B_j = Q16 R_j + cdel * (common weight up to j) + retw [j >= pt]:
+            // find the first listed position with B > T, then the segment
+            // before it holds no common neighbour.
+            uint64_t E = 0, Eprev = CW;
+            uint32_t seg_lo = 0, seg_hi = d, lastpos = 0, left = cnt, page = stored;
+            bool found = false, any = false;
+            while (true) {
+              for (uint32_t c = 0; c < page; c += G) {
                 const uint32_t k = c + gl;
-                const bool act = k < cnt;
+                const bool act = k < page;
                 const uint32_t p = act ? lpos[k] : 0u;
                 const uint64_t wk = act ? (uint64_t)lw[k] : 0ull;
                 const uint64_t inc = grp_incl_scan<G>(wk, gl);
@@ -404,24 +426,33 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   Eprev = grp_bcast<G>(Ek - wk, f);
                   seg_hi = (uint32_t)grp_bcast_i32<G>((int32_t)p, f);
                   const uint32_t pprev = (uint32_t)grp_bcast_i32<G>((int32_t)p, f > 0 ? f - 1 : 0);
-                  seg_lo = f > 0 ? pprev + 1 : (c > 0 ? lastpos + 1 : 0u);
+                  seg_lo = f > 0 ? pprev + 1 : (any ? lastpos + 1 : 0u);
                   found = true;
                   break;
                 }
-                const uint32_t nact = min((uint32_t)G, cnt - c);
+                const uint32_t nact = min((uint32_t)G, page - c);
                 lastpos = (uint32_t)grp_bcast_i32<G>((int32_t)p, (int)nact - 1);
+                any = true;
                 E += grp_bcast<G>(inc, G - 1);
               }
-              if (!found) {
-                seg_lo = cnt > 0 ? lastpos + 1 : 0u;
-                seg_hi = d;
-                Eprev = CW;
-              }
-              const uint64_t base = cdel * Eprev;
-              jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
-                return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
-              });
+              left -= page;
+              if (found || left == 0) break;
+              // the draw lies beyond this page: list the next one
+              stored = 0;
+              const uint32_t from = resume;
+              gen(from);
+              page = stored;
+              if (page == 0) break;  // unreachable: `left` hits remain after `from`
             }
+            if (!found) {
+              seg_lo = any ? lastpos + 1 : 0u;
+              seg_hi = d;
+              Eprev = CW;
+            }
+            const uint64_t base = cdel * Eprev;
+            jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
+              return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
+            });
           }
         }
         if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
