@@ -322,3 +322,63 @@ def poisson_arrivals(n: int, rate: float, seed: int = 11) -> np.ndarray:
     """Open-loop arrival times (seconds from 0) of a Poisson process."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def chung_lu_device(n: int, n_edges: int, gamma: float, mean_deg: float, w_max: float, wrange=(1, 255),
+                    seed: int = 0, device="cuda", chunk: int = 1 << 27, log=None):
+    """The Chung-Lu construction of chung_lu(), run with torch on a GPU for
+    graphs too large for host-side sorting (e.g. 1e9 edge samples).  Same
+    recipe; the random stream is torch's (seeded), so the graph differs from
+    the numpy version with the same seed.  Returns device tensors
+    (offsets int64[n+1], dst int32[m], weights int32[m] holding uint32 values)."""
+    import torch
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    w = torch.from_numpy(chung_lu_weights(n, gamma, mean_deg, w_max)).to(dev)
+    cdf = torch.cumsum(w, 0)
+    cdf /= cdf[-1].clone()
+    del w
+    keys = []
+    for off in range(0, n_edges, chunk):
+        k = min(chunk, n_edges - off)
+        a = torch.searchsorted(cdf, torch.rand(k, generator=gen, device=dev, dtype=torch.float64), right=True)
+        b = torch.searchsorted(cdf, torch.rand(k, generator=gen, device=dev, dtype=torch.float64), right=True)
+        a.clamp_(max=n - 1)
+        b.clamp_(max=n - 1)
+        lo = torch.minimum(a, b)
+        hi = torch.maximum(a, b)
+        del a, b
+        keep = lo != hi
+        keys.append(((lo << 32) | hi)[keep])
+        del lo, hi, keep
+    del cdf
+    key = torch.unique(torch.cat(keys))  # sorted, duplicates dropped
+    del keys
+    if log:
+        log(f"unique undirected edges {key.numel()}")
+    lo = key >> 32
+    hi = key & 0xFFFFFFFF
+    del key
+    ew = torch.randint(wrange[0], wrange[1] + 1, (lo.numel(),), generator=gen, device=dev, dtype=torch.int32)
+    perm = torch.randperm(n, generator=gen, device=dev)
+    lo = perm[lo]
+    hi = perm[hi]
+    del perm
+    src = torch.cat([lo, hi])
+    dst = torch.cat([hi, lo])
+    del lo, hi
+    ew = torch.cat([ew, ew])
+    skey = (src << 32) | dst
+    del dst
+    skey, order = torch.sort(skey)
+    ew = ew[order]
+    del order
+    src = skey >> 32
+    D = (skey & 0xFFFFFFFF).to(torch.int32)
+    del skey
+    counts = torch.bincount(src, minlength=n)
+    del src
+    O = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    torch.cumsum(counts, 0, out=O[1:])
+    return O, D, ew

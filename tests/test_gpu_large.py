@@ -1,0 +1,80 @@
+"""Large inputs: a graph with more than 2^31 CSR entries (64-bit offsets in every
+kernel, paged common-neighbour lists of ~46k entries per step) and a hub-heavy
+power-law graph shaped like the 20M-node workload at 1/20 scale, both checked
+against the oracle on sampled walks."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2110_06196_amd as n2v  # noqa: E402
+
+
+def _host(O, D, W):
+    Oh = O.cpu().numpy().view(np.uint64)
+    Dh = D.cpu().numpy()
+    Wh = None if W is None else W.cpu().numpy().view(np.uint32)
+    return Oh, Dh, Wh
+
+
+def _check(g, host, n, starts, L, kind, p, q, seed, rows, threads=16):
+    S = torch.from_numpy(np.asarray(starts, dtype=np.int32)).cuda()
+    if kind == n2v.N2V_FIRST_ORDER:
+        Y, lens = n2v.n2v_walks_first_order(g, S, 1, L, seed)
+    else:
+        Y, lens = n2v.n2v_walks_node2vec(g, S, 1, L, p, q, seed)
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(rows).cuda()
+    Yg = Y.index_select(0, idx).cpu().numpy()
+    lg = lens.index_select(0, idx).cpu().numpy()
+    Yo, lo = oracle.walks_threaded(*host, starts, 1, L, kind, p, q, seed, 0, rows, threads)
+    assert np.array_equal(Yg, Yo) and np.array_equal(lg, lo), (kind, p, q)
+    return int((lens.to(torch.int64) - 1).clamp(min=0).sum().item())
+
+
+def test_more_than_2_31_entries():
+    n = 46400  # complete graph without self-loops: n (n - 1) = 2,152,913,600 entries
+    m = n * (n - 1)
+    assert m > 2**31
+    dev = torch.device("cuda")
+    O = torch.arange(n + 1, dtype=torch.int64, device=dev) * (n - 1)
+    D = torch.empty(m, dtype=torch.int32, device=dev)
+    ar = torch.arange(n, dtype=torch.int32, device=dev)
+    for v in range(0, n, 4096):  # row v = [0, n) without v, built in slabs
+        k = min(4096, n - v)
+        rows = ar.repeat(k, 1)
+        keep = rows != torch.arange(v, v + k, dtype=torch.int32, device=dev)[:, None]
+        D[int(O[v]):int(O[v + k])] = rows[keep]
+    del ar
+    g = n2v.n2v_graph_upload(O, D, None)
+    info = n2v.n2v_graph_info(g)
+    assert info["n_entries"] == m and info["max_degree"] == n - 1
+    host = _host(O, D, None)
+    starts = np.concatenate([np.arange(0, n, 997), [n - 1]]).astype(np.int32)
+    rows = np.arange(starts.size, dtype=np.int64)
+    _check(g, host, n, starts, 8, n2v.N2V_FIRST_ORDER, 1.0, 1.0, 5, rows)
+    _check(g, host, n, starts, 8, n2v.N2V_NODE2VEC, 2.0, 1.0, 6, rows)
+    _check(g, host, n, starts[:24], 6, n2v.N2V_NODE2VEC, 0.5, 2.0, 7, rows[:24])
+    n2v.n2v_graph_release(g)
+
+
+def test_power_law_hubs_sampled():
+    n, ne = 1_000_000, 50_000_000
+    O, D, W = synth.chung_lu_device(n, ne, 2.2, 2.0 * ne / n, 1.0e5, (1, 255), seed=3)
+    g = n2v.n2v_graph_upload(O, D, W)
+    info = n2v.n2v_graph_info(g)
+    assert info["max_degree"] > 30000 and info["prefix_bytes"] == 4
+    host = _host(O, D, W)
+    starts = np.arange(n, dtype=np.int32)
+    rows = np.linspace(0, n - 1, 400).astype(np.int64)
+    for kind, p, q in [(n2v.N2V_FIRST_ORDER, 1.0, 1.0), (n2v.N2V_NODE2VEC, 1.0, 2.0), (n2v.N2V_NODE2VEC, 0.25, 4.0)]:
+        steps = _check(g, host, n, starts, 40, kind, p, q, 42, rows)
+        assert steps > 0
+    n2v.n2v_graph_release(g)
