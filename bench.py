@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--runs", default="1,1;0.25,4", help="(p,q) pairs, ';'-separated")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--walk-len", type=int, default=100)
-    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served"],
+    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served", "big"],
                     help="chung_lu_1m: plain launches (default); batched: 64 graphs x 4096 requests, one "
                          "launch per request vs one persistent hipGraph launch; served: the same requests "
                          "under Poisson arrivals, server vs one launch per request")
@@ -275,6 +275,9 @@ def main():
         return
     if args.config == "served":
         bench_served(args)
+        return
+    if args.config == "big":
+        bench_big(args)
         return
     import torch
     import paper_2110_06196_amd as n2v
@@ -671,6 +674,70 @@ def bench_served(args):
         "rates": results, "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_big(args):
+    """20M nodes, 1e9 undirected edge samples (gamma 2.2, max expected degree 2e6,
+    weights U[1,255]), generated on the GPU; first-order and node2vec (1, 2),
+    one walk of 80 slots per node, seed 42; 300 sampled walks per run checked
+    against the oracle."""
+    import torch
+    import oracle
+    import paper_2110_06196_amd as n2v
+    import synth
+    dev = torch.device("cuda:0")
+    n, ne = 20_000_000, 1_000_000_000
+    t0 = time.time()
+    O, D, W = synth.chung_lu_device(n, ne, 2.2, 2.0 * ne / n, 2.0e6, (1, 255), seed=3)
+    torch.cuda.synchronize()
+    print(f"[bench] graph generated in {time.time() - t0:.1f}s, m={D.numel()}", file=sys.stderr, flush=True)
+    g = n2v.n2v_graph_upload(O, D, W)
+    info = n2v.n2v_graph_info(g)
+    L = 80
+    S = torch.arange(n, dtype=torch.int32, device=dev)
+    Y = torch.empty((n, L), dtype=torch.int32, device=dev)
+    lens = torch.empty(n, dtype=torch.int32, device=dev)
+    host = (O.cpu().numpy().view(np.uint64), D.cpu().numpy(), W.cpu().numpy().view(np.uint32))
+    rows = np.linspace(0, n - 1, 300).astype(np.int64)
+    runs = []
+    for kind, p, q in [(n2v.N2V_FIRST_ORDER, 1.0, 1.0), (n2v.N2V_NODE2VEC, 1.0, 2.0)]:
+        ms = []
+        for k in range(args.warmup + args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if kind == n2v.N2V_FIRST_ORDER:
+                n2v.n2v_walks_first_order(g, S, 1, L, 42, 0, Y, lens)
+            else:
+                n2v.n2v_walks_node2vec(g, S, 1, L, p, q, 42, 0, Y, lens)
+            e1.record()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                ms.append(e0.elapsed_time(e1))
+            print(f"[bench] kind {kind} p {p} q {q} launch {k}: {e0.elapsed_time(e1):.1f} ms", file=sys.stderr,
+                  flush=True)
+        steps = int((lens.to(torch.int64) - 1).clamp(min=0).sum().item())
+        idx = torch.from_numpy(rows).to(dev)
+        Yg = Y.index_select(0, idx).cpu().numpy()
+        lg = lens.index_select(0, idx).cpu().numpy()
+        t1 = time.perf_counter()
+        Yo, lo = oracle.walks_threaded(*host, S.cpu().numpy(), 1, L, kind, p, q, 42, 0, rows, min(16, os.cpu_count()))
+        ct = time.perf_counter() - t1
+        csteps = int(np.maximum(lo.astype(np.int64) - 1, 0).sum())
+        runs.append({"kind": "first_order" if kind == 0 else "node2vec", "p": p, "q": q,
+                     "mean_ms": float(np.mean(ms)), "steps": steps, "steps_per_s": steps / (np.mean(ms) / 1e3),
+                     "oracle_sample_mismatching_rows": int(((Yg != Yo).any(1) | (lg != lo)).sum()),
+                     "oracle_steps_per_s": csteps / ct})
+    out = {"metric": METRIC, "value": runs[1]["steps_per_s"], "unit": "walk steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": runs[1]["mean_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "plain first-order and node2vec (p=1, q=2) on a Chung-Lu graph: 20M nodes, 1e9 "
+                                  "undirected edge samples (gamma 2.2, max expected degree 2e6), weights U[1,255], "
+                                  "one walk of 80 slots per node, seed 42",
+                      "n_entries": int(D.numel()), "max_degree": info["max_degree"],
+                      "stationary_mean_degree": info["sum_deg_sq"] / max(1, info["n_entries"])},
+           "runs": runs, "kernel_source_hash": kernel_source_hash()}
+    print(json.dumps(out), flush=True)
+    n2v.n2v_graph_release(g)
 
 
 if __name__ == "__main__":
