@@ -88,10 +88,11 @@ typedef struct {
 } n2v_tuning_t;
 
 enum {
-  N2V_ROUTE_AUTO = 0,     /* per step, the cheaper of PROBE and STREAM by a latency estimate */
+  N2V_ROUTE_AUTO = 0,     /* per step, the cheapest of PROBE, STREAM and MERGE by a latency estimate */
   N2V_ROUTE_TWO_PASS = 1, /* stream the biased weights of N(v) twice (block sums, then one block) */
   N2V_ROUTE_PROBE = 2,    /* bisect every node of N(t) into N(v) to list the common neighbours */
-  N2V_ROUTE_STREAM = 3    /* stream N(v) and test each candidate against N(t) */
+  N2V_ROUTE_STREAM = 3,   /* stream N(v) and test each candidate against N(t) */
+  N2V_ROUTE_MERGE = 4     /* merge the two sorted rows, a window of N(t) at a time in LDS */
 };
 
 enum {

@@ -23,7 +23,7 @@ N2V_ERR_INVALID_ARG, N2V_ERR_UNSORTED, N2V_ERR_OVERFLOW = -1, -2, -3
 N2V_ERR_NOMEM, N2V_ERR_HIP, N2V_ERR_BAD_HANDLE, N2V_ERR_REJECTED = -4, -5, -6, -7
 N2V_FIRST_ORDER, N2V_NODE2VEC = 0, 1
 N2V_TUNE_GENERIC_ONLY = 1
-N2V_ROUTE_AUTO, N2V_ROUTE_TWO_PASS, N2V_ROUTE_PROBE, N2V_ROUTE_STREAM = 0, 1, 2, 3
+N2V_ROUTE_AUTO, N2V_ROUTE_TWO_PASS, N2V_ROUTE_PROBE, N2V_ROUTE_STREAM, N2V_ROUTE_MERGE = 0, 1, 2, 3, 4
 N2V_BATCH_AUTOTUNE = 1
 
 _STATUS = {

@@ -102,8 +102,7 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
     c.mode = (int)g_tune.route;
   }
   // keep the per-block LDS inside the hardware limit
-  const size_t gpb = 256 / (size_t)c.lanes_per_walker;
-  auto bytes = [&]() { return gpb * (2 * (size_t)c.lds_tile + 2 * (size_t)c.list_cap) * 4; };
+  auto bytes = [&]() { return block_lds_bytes(c.lanes_per_walker, c.lds_tile, c.list_cap); };
   while (bytes() > di.lds_per_block_max && (c.lds_tile > 1 || c.list_cap > 1)) {
     if (c.lds_tile >= c.list_cap && c.lds_tile > 1) c.lds_tile /= 2;
     else c.list_cap /= 2;
@@ -121,8 +120,7 @@ void apply_tuning_override(LaunchCfg* c, const DevInfo& di) {
     c->mode = (int)g_tune.route;
   }
   if (c->lanes_per_walker < 16) c->lanes_per_walker = 16;  // the queue kernel's smallest group
-  const size_t gpb = 256 / (size_t)c->lanes_per_walker;
-  auto bytes = [&]() { return gpb * (2 * (size_t)c->lds_tile + 2 * (size_t)c->list_cap) * 4; };
+  auto bytes = [&]() { return block_lds_bytes(c->lanes_per_walker, c->lds_tile, c->list_cap); };
   while (bytes() > di.lds_per_block_max && (c->lds_tile > 1 || c->list_cap > 1)) {
     if (c->lds_tile >= c->list_cap && c->lds_tile > 1) c->lds_tile /= 2;
     else c->list_cap /= 2;
@@ -300,7 +298,7 @@ int n2v_set_tuning(const n2v_tuning_t* tuning) {
       return fail(N2V_ERR_INVALID_ARG, "lanes_per_walker must be 4, 8, 16, 32 or 64");
     if (tuning->lds_tile > (1u << 16) || tuning->list_cap > (1u << 16))
       return fail(N2V_ERR_INVALID_ARG, "lds_tile / list_cap too large");
-    if (tuning->route > N2V_ROUTE_STREAM) return fail(N2V_ERR_INVALID_ARG, "unknown route");
+    if (tuning->route > N2V_ROUTE_MERGE) return fail(N2V_ERR_INVALID_ARG, "unknown route");
     if (tuning->flags & ~(uint32_t)N2V_TUNE_GENERIC_ONLY) return fail(N2V_ERR_INVALID_ARG, "unknown flags");
   }
   std::lock_guard<std::mutex> lk(g_mu);

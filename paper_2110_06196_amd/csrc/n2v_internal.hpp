@@ -58,6 +58,16 @@ struct LaunchCfg {
   int grid_blocks = 0;        // 0 = derive from occupancy
 };
 
+// LDS words per walker group of g lanes: two staging tiles of the previous
+// row, the common-neighbour list (positions, weights) and a g-entry merge
+// window.
+__host__ __device__ constexpr int group_lds_words(int tile, int cap, int g) { return 2 * tile + 2 * cap + g; }
+
+// LDS bytes of a 256-thread block for a launch shape.
+inline size_t block_lds_bytes(int lanes_per_walker, int tile, int cap) {
+  return (size_t)(256 / lanes_per_walker) * (size_t)group_lds_words(tile, cap, lanes_per_walker) * 4;
+}
+
 // Device facts used to size grids.
 struct DevInfo {
   int device = 0;

@@ -211,8 +211,7 @@ int autotune(BatchPlan* p) {
     c.lanes_per_walker = sh[0];
     c.lds_tile = sh[1];
     c.list_cap = sh[2];
-    const size_t gpb = 256 / (size_t)c.lanes_per_walker;
-    if (gpb * (2 * (size_t)c.lds_tile + 2 * (size_t)c.list_cap) * 4 > p->di.lds_per_block_max) continue;
+    if (block_lds_bytes(c.lanes_per_walker, c.lds_tile, c.list_cap) > p->di.lds_per_block_max) continue;
     float ms_min = 1e30f;
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
       e = hipEventRecord(e0, st);

@@ -141,7 +141,7 @@ __device__ __forceinline__ bool global_contains(const int32_t* __restrict__ A, u
 // ---------------------------------------------------------------------------
 // node2vec kernel: G lanes per walker.
 // ---------------------------------------------------------------------------
-enum { kModeAuto = 0, kModeTwoPass = 1, kModeProbe = 2, kModeStream = 3 };
+enum { kModeAuto = 0, kModeTwoPass = 1, kModeProbe = 2, kModeStream = 3, kModeMerge = 4 };
 
 __device__ __forceinline__ uint32_t ceil_log2p1(uint32_t x) {  // ceil(log2(x + 1))
   return 32u - (uint32_t)__clz(x);
@@ -174,11 +174,9 @@ __device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl,
 // G / nk lanes assigned to one key probe k evenly spaced points per round, so
 // a search takes about log_{k+1}(n) dependent loads instead of log2(n).
 // Returns, in lane l < nk, whether its key is in A and (if so) its index.
-// LDS words per walker group: two staging tiles and the list (positions, weights).
-__host__ __device__ constexpr int group_lds_words(int tile, int cap) { return 2 * tile + 2 * cap; }
 
 // One whole walk (row w of request a) by one group of G lanes; mem is the
-// group's LDS region of group_lds_words(tile, cap) words.
+// group's LDS region of group_lds_words(tile, cap, G) words.
 template <int G, bool WEIGHTED, typename RT>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
                                            int mode_knob) {
@@ -189,6 +187,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   int32_t* const bufB = bufA + tile;
   uint32_t* const lpos = (uint32_t*)(bufB + tile);
   uint32_t* const lw = lpos + cap;
+  int32_t* const win = (int32_t*)(lw + cap);
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const uint32_t* __restrict__ W = a.g.W;
@@ -303,9 +302,12 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           int mode = mode_knob;
           if (mode == kModeAuto) {
             // dependent-latency estimate: global load = 100, LDS load = 15
-            const uint32_t probe = ((td + 1 + G - 1) / G) * ceil_log2p1(d) * 100u;
-            const uint32_t stream = ((d + G - 1) / G) * (100u + ceil_log2p1(td) * (t_in_lds ? 15u : 100u));
-            mode = probe < stream ? kModeProbe : kModeStream;
+            const uint64_t probe = (uint64_t)((td + 1 + G - 1) / G) * ceil_log2p1(d) * 100u;
+            const uint64_t stream =
+                (uint64_t)((d + G - 1) / G) * (100u + ceil_log2p1(td) * (t_in_lds ? 15u : 100u));
+            const uint64_t merge = (uint64_t)(((uint64_t)d + td + G - 1) / G) * (t_in_lds ? 130u : 220u);
+            mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
+                                  : (stream <= merge ? kModeStream : kModeMerge);
           }
           if (mode == kModeTwoPass) {
             two_pass();
@@ -366,6 +368,56 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   // a self-loop at t puts t in N(t): that candidate is a return, not common
                   append(hit && !tkey && y != t, pos, c);
                 }
+              } else if (mode == kModeMerge) {
+                // co-iterate N(v) (keys, global) and N(t) (B): invariant
+                // "every element of B before ib is below N(v)[ia]"; a window
+                // of G elements of B goes to LDS, every lane whose candidate is
+                // at most the window's last element is decided by bisecting
+                // the window; each round advances ia by G or ib by G.
+                const bool stg = first && d <= (uint32_t)tile;
+                auto Bv = [&](uint32_t k) -> int32_t { return t_in_lds ? cur[k] : D[tlo + k]; };
+                uint32_t ia = from, ib = 0;
+                if (ia > 0 && ia < d) {
+                  const int32_t a0 = D[lo + ia];
+                  ib = gary_first<G>(0u, td, gl, gbase, [&](uint32_t k) { return Bv(k) >= a0; });
+                }
+                while (ia < d) {
+                  if (!first && stored >= (uint32_t)cap) break;
+                  const uint32_t j = ia + gl;
+                  const bool act = j < d;
+                  int32_t x = 0x7FFFFFFF;
+                  if (act) {
+                    x = D[lo + j];
+                    if (stg) nxt[j] = x;
+                  }
+                  const uint32_t nb = ib < td ? min((uint32_t)G, td - ib) : 0u;
+                  const int32_t bval = (uint32_t)gl < nb ? Bv(ib + gl) : 0x7FFFFFFF;
+                  win[gl] = bval;
+                  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                  // B beyond this window is empty when nb < G: then every candidate is decided
+                  const int32_t blast = nb == (uint32_t)G ? grp_bcast_i32<G>(bval, G - 1) : 0x7FFFFFFF;
+                  const bool res = act && x <= blast;
+                  const bool isret = res && x == t;
+                  const uint64_t mt = grp_ballot<G>(isret, gbase);
+                  if (mt) {
+                    has_t = true;
+                    pt = ia + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
+                  }
+                  const bool in_t = res && !isret && nb > 0 && lds_contains(win, nb, x);
+                  append(in_t, j, ia);
+                  const uint32_t nact = min((uint32_t)G, d - ia);
+                  const uint32_t nres = (uint32_t)__popcll(grp_ballot<G>(res, gbase));
+                  if (nres == nact) {
+                    ia += nact;
+                  } else {
+                    ia += nres;  // decided lanes are a prefix: the candidates are sorted
+                    ib += (uint32_t)G;
+                  }
+                  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                if (first) staged = stg;
               } else {
                 const bool stg = first && d <= (uint32_t)tile;
                 for (uint32_t c = from; c < d; c += G) {
@@ -494,7 +546,7 @@ __global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 8 :
   extern __shared__ int32_t lds[];
   const int gib = threadIdx.x / G;
   const int gpb = blockDim.x / G;
-  int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap);
+  int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap, G);
   const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
   for (uint64_t w = (uint64_t)blockIdx.x * gpb + gib; w < a.nwalks; w += ngroups)
     group_walk<G, WEIGHTED, RT>(a, w, mem, tile, cap, mode_knob);
@@ -528,7 +580,7 @@ __global__ __launch_bounds__(256, G == 64 ? 8 : 1) void k_walk_queue(const WalkA
   extern __shared__ int32_t lds[];
   const int gl = (threadIdx.x & 63) & (G - 1);
   const int gib = threadIdx.x / G;
-  int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap);
+  int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap, G);
   while (true) {
     uint32_t c = 0;
     if (gl == 0) c = atomicAdd(head, 1u);
@@ -587,7 +639,7 @@ template <int G, bool WEIGHTED, typename RT>
 hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   auto k = k_walk_n2v<G, WEIGHTED, RT>;
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap) * sizeof(int32_t);
+  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cfg.mode);
   return hipGetLastError();
@@ -609,7 +661,7 @@ hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nch
                     const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   auto k = k_walk_queue<G>;
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap) * sizeof(int32_t);
+  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, ((uint64_t)nchunks + gpb - 1) / gpb, di);
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, head);
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, reqs, chunks, nchunks, head, cfg.lds_tile,
@@ -622,7 +674,7 @@ hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nch
 int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks) {
   const int G = cfg.lanes_per_walker == 16 ? 16 : (cfg.lanes_per_walker == 32 ? 32 : 64);
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap) * sizeof(int32_t);
+  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   const uint64_t work = ((uint64_t)nchunks + gpb - 1) / gpb;
   if (G == 16) return grid_for(k_walk_queue<16>, lds, work, di);
   if (G == 32) return grid_for(k_walk_queue<32>, lds, work, di);

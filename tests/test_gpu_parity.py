@@ -95,7 +95,7 @@ def test_tuning_points_and_specialisations_identical():
     cases = [(NV, 0.25, 4.0), (NV, 2.0, 1.0), (NV, 1.0, 1.0), (FO, 1.0, 1.0), (NV, 0.5, 2.0)]
     grid = [(lanes, tile, cap, route, flags)
             for lanes in (4, 8, 16, 32, 64) for tile in (1, 2048) for cap in (1, 512)
-            for route in (0, 1, 2, 3) for flags in (0, n2v.N2V_TUNE_GENERIC_ONLY)]
+            for route in (0, 1, 2, 3, 4) for flags in (0, n2v.N2V_TUNE_GENERIC_ONLY)]
     for ww in (W, None):
         _tuning_sweep(O, D, ww, rows, 30, cases, grid)
 
@@ -108,7 +108,7 @@ def test_hub_rows_all_routes():
     rows = np.arange(0, len(O) - 1, 41)
     cases = [(NV, 0.25, 4.0), (NV, 4.0, 0.25), (NV, 2.0, 1.0)]
     grid = [(lanes, tile, cap, route, 0)
-            for lanes in (4, 64) for tile in (1, 4096) for cap in (1, 4096) for route in (1, 2, 3)]
+            for lanes in (4, 64) for tile in (1, 4096) for cap in (1, 4096) for route in (1, 2, 3, 4)]
     _tuning_sweep(O, D, W, rows, 24, cases, grid)
 
 
