@@ -177,6 +177,35 @@ __device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl,
 
 // One whole walk (row w of request a) by one group of G lanes; mem is the
 // group's LDS region of group_lds_words(tile, cap, G) words.
+// Splitters of a long sorted row A[0..n) (n >= 4G): the group loads A[l n / G]
+// for its G lanes into LDS (one coalesced round), and every lane can then
+// bisect a key among the splitters in LDS and the key's 1/G slice of A in
+// global memory.  spl must hold G entries.
+template <int G>
+__device__ __forceinline__ void load_splitters(const int32_t* __restrict__ A, uint32_t n, int32_t* spl, int gl) {
+  spl[gl] = A[(uint32_t)(((uint64_t)gl * n) / G)];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First index j in [0, n) with A[j] >= y (n if none), searching only the
+// slice between the splitters around y.
+template <int G>
+__device__ __forceinline__ uint32_t lower_bound_split(const int32_t* __restrict__ A, uint32_t n,
+                                                      const int32_t* spl, int32_t y) {
+  // largest splitter index l with spl[l] <= y (spl[0] = A[0]); none -> y < A[0]
+  int lo = 0, hi = G;  // first l with spl[l] > y lies in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (spl[mid] <= y) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo == 0) return 0;
+  const uint32_t b = (uint32_t)(((uint64_t)(lo - 1) * n) / G);
+  const uint32_t e = lo < G ? (uint32_t)(((uint64_t)lo * n) / G) : n;
+  return b + lower_bound_i32(A + b, e - b, y);
+}
+
 template <int G, bool WEIGHTED, typename RT>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
                                            int mode_knob) {
@@ -302,9 +331,14 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           int mode = mode_knob;
           if (mode == kModeAuto) {
             // dependent-latency estimate: global load = 100, LDS load = 15
-            const uint64_t probe = (uint64_t)((td + 1 + G - 1) / G) * ceil_log2p1(d) * 100u;
-            const uint64_t stream =
-                (uint64_t)((d + G - 1) / G) * (100u + ceil_log2p1(td) * (t_in_lds ? 15u : 100u));
+            // splitters cut a bisection of a row of n >= 4G by log2(G) global rounds for one round
+            auto glob = [&](uint32_t n) -> uint32_t {
+              return n >= 4u * G ? 100u * (ceil_log2p1(n) - ceil_log2p1(G - 1)) + 15u * ceil_log2p1(G) : 100u * ceil_log2p1(n);
+            };
+            const uint64_t probe = (uint64_t)((td + 1 + G - 1) / G) * glob(d) + (d >= 4u * G ? 100u : 0u);
+            const uint64_t stream = (uint64_t)((d + G - 1) / G) *
+                                        (100u + (t_in_lds ? 15u * ceil_log2p1(td) : glob(td))) +
+                                    (!t_in_lds && td >= 4u * G ? 100u : 0u);
             const uint64_t merge = (uint64_t)(((uint64_t)d + td + G - 1) / G) * (t_in_lds ? 130u : 220u);
             mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
                                   : (stream <= merge ? kModeStream : kModeMerge);
@@ -347,6 +381,8 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             auto gen = [&](uint32_t from) {
               if (mode == kModeProbe) {
                 const uint32_t nk = td + 1;
+                const bool split = d >= 4u * G;
+                if (split) load_splitters<G>(D + lo, d, win, gl);
                 for (uint32_t c = from; c < nk; c += G) {
                   if (!first && stored >= (uint32_t)cap) break;
                   const uint32_t k = c + gl;
@@ -357,7 +393,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   uint32_t pos = 0;
                   bool hit = false;
                   if (act) {
-                    pos = lower_bound_i32(D + lo, d, y);
+                    pos = split ? lower_bound_split<G>(D + lo, d, win, y) : lower_bound_i32(D + lo, d, y);
                     hit = pos < d && D[lo + pos] == y;
                   }
                   const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
@@ -420,6 +456,8 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                 if (first) staged = stg;
               } else {
                 const bool stg = first && d <= (uint32_t)tile;
+                const bool split = !t_in_lds && td >= 4u * G;
+                if (split) load_splitters<G>(D + tlo, td, win, gl);
                 for (uint32_t c = from; c < d; c += G) {
                   if (!first && stored >= (uint32_t)cap) break;
                   const uint32_t j = c + gl;
@@ -439,7 +477,12 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   if (t_in_lds) {
                     in_t = act && !isret && lds_contains(cur, td, x);
                   } else {
-                    in_t = act && !isret && global_contains(D + tlo, td, x);
+                    if (split) {
+                      const uint32_t q = act && !isret ? lower_bound_split<G>(D + tlo, td, win, x) : td;
+                      in_t = q < td && D[tlo + q] == x;
+                    } else {
+                      in_t = act && !isret && global_contains(D + tlo, td, x);
+                    }
                   }
                   append(act && !isret && in_t, j, c);
                 }
