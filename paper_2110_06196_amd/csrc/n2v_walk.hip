@@ -585,7 +585,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
 }
 
 template <int G, bool WEIGHTED, typename RT>
-__global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 8 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
+__global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 7 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
   extern __shared__ int32_t lds[];
   const int gib = threadIdx.x / G;
   const int gpb = blockDim.x / G;
@@ -616,7 +616,7 @@ __device__ __forceinline__ void lane_dispatch(const WalkArgs& a, uint64_t w) {
 }
 
 template <int G>
-__global__ __launch_bounds__(256, G == 64 ? 8 : 1) void k_walk_queue(const WalkArgs* __restrict__ reqs,
+__global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkArgs* __restrict__ reqs,
                                                     const QueueChunk* __restrict__ chunks, uint32_t nchunks,
                                                     uint32_t* __restrict__ head, int tile, int cap,
                                                     int mode_knob) {
