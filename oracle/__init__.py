@@ -79,6 +79,12 @@ def lib():
             L.n2vo_walks_subset.restype = ctypes.c_int
             L.n2vo_walks.argtypes = common + [i32p, i32p]
             L.n2vo_walks.restype = ctypes.c_int
+            L.n2vo_suss.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_uint32, u32p]
+            L.n2vo_suss.restype = None
+            L.n2vo_walks_approx_subset.argtypes = (common[:12] + [ctypes.c_uint32] + common[12:] +
+                                                   [i64p, ctypes.c_int64, i32p, i32p])
+            L.n2vo_walks_approx_subset.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -150,9 +156,17 @@ def select(b, T: int) -> int:
     return int(lib().n2vo_select(_p(bb, ctypes.c_uint64), bb.size, T))
 
 
+def suss(seed: int, step: int, wid: int, d: int, k: int):
+    """Sorted Unique Sub-Sampling: k positions in [0, d) (d > k)."""
+    out = np.zeros(k, dtype=np.uint32)
+    lib().n2vo_suss(seed, step, wid, d, k, _p(out, ctypes.c_uint32))
+    return out
+
+
 def walks(offsets, dst, weights, starts, walks_per_start: int, walk_len: int, kind: int,
-          p: float = 1.0, q: float = 1.0, seed: int = 0, walk_id_base: int = 0, rows=None):
+          p: float = 1.0, q: float = 1.0, seed: int = 0, walk_id_base: int = 0, rows=None, k_approx: int = 0):
     """Run the oracle.  rows: None for all walks, else the walk-row indices to produce.
+    k_approx > 0: approximated walks (SUSS sub-sample of k_approx neighbours per step).
 
     Returns (Y int32[nrows][walk_len], lens int32[nrows])."""
     O, D, W = _csr(offsets, dst, weights)
@@ -161,7 +175,15 @@ def walks(offsets, dst, weights, starts, walks_per_start: int, walk_len: int, ki
     args = (_p(O, ctypes.c_uint64), n, _p(D, ctypes.c_int32), D.size, _p(W, ctypes.c_uint32),
             _p(S, ctypes.c_int32), S.size, walks_per_start, walk_len, kind, float(p), float(q),
             seed, walk_id_base)
-    if rows is None:
+    if k_approx:
+        if rows is None:
+            rows = np.arange(S.size * walks_per_start, dtype=np.int64)
+        idx = np.ascontiguousarray(rows, dtype=np.int64)
+        Y = np.empty((idx.size, walk_len), dtype=np.int32)
+        lens = np.empty(idx.size, dtype=np.int32)
+        rc = lib().n2vo_walks_approx_subset(*args[:12], k_approx, *args[12:], _p(idx, ctypes.c_int64), idx.size,
+                                            _p(Y, ctypes.c_int32), _p(lens, ctypes.c_int32))
+    elif rows is None:
         nw = S.size * walks_per_start
         Y = np.empty((nw, walk_len), dtype=np.int32)
         lens = np.empty(nw, dtype=np.int32)
@@ -178,7 +200,7 @@ def walks(offsets, dst, weights, starts, walks_per_start: int, walk_len: int, ki
 
 
 def walks_threaded(offsets, dst, weights, starts, walks_per_start, walk_len, kind, p=1.0, q=1.0,
-                   seed=0, walk_id_base=0, rows=None, threads=1):
+                   seed=0, walk_id_base=0, rows=None, threads=1, k_approx=0):
     """Same as walks(), with disjoint slices of `rows` handed to `threads` OS threads.
 
     ctypes releases the GIL during each call, so the slices run concurrently;
@@ -192,7 +214,7 @@ def walks_threaded(offsets, dst, weights, starts, walks_per_start, walk_len, kin
 
     def run(i):
         out[i] = walks(offsets, dst, weights, starts, walks_per_start, walk_len, kind, p, q, seed,
-                       walk_id_base, parts[i])
+                       walk_id_base, parts[i], k_approx)
 
     ts = [threading.Thread(target=run, args=(i,)) for i in range(threads)]
     for t in ts:

@@ -142,25 +142,69 @@ int64_t n2vo_select(const uint64_t* b, int64_t d, uint64_t T) {
   return d;
 }
 
-/* One walk, slots Y[0..L): start, then up to L-1 steps, then -1 padding. */
+/* ------------------------------------------------------------------------ */
+/* Sorted Unique Sub-Sampling (Methods, "Approximated RWs").                 */
+/* ------------------------------------------------------------------------ */
+void n2vo_suss(uint64_t seed, uint32_t step, uint64_t wid, uint32_t d, uint32_t k, uint32_t* pos) {
+  uint32_t len = d / k;
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (uint32_t i = 0; i < k; ++i) {
+    uint32_t ctr[4] = {step, (uint32_t)wid, (uint32_t)(wid >> 32), 1u + i / 2u};
+    uint32_t out[4];
+    n2vo_philox4x32_10(ctr, key, out);
+    uint64_t r = (uint64_t)out[2 * (i % 2)] | ((uint64_t)out[2 * (i % 2) + 1] << 32);
+    uint32_t start = i * len;
+    uint32_t blen = (i + 1 < k) ? len : d - start; /* the last bucket takes the remainder */
+    pos[i] = start + (uint32_t)n2vo_scale(r, blen);
+  }
+}
+
+/* Biased weights of the sub-sampled candidates N(v)[pos[i]], i < k. */
+static void sub_weights(const uint64_t* O, const int32_t* D, const uint32_t* W, int32_t t, int32_t v,
+                        int second_order, uint32_t P16, uint32_t Q16, const uint32_t* pos, uint32_t k,
+                        uint64_t* b) {
+  for (uint32_t i = 0; i < k; ++i) {
+    uint64_t e = O[v] + pos[i];
+    int32_t x = D[e];
+    uint64_t w = W ? (uint64_t)W[e] : 1u;
+    uint64_t a;
+    if (!second_order || t < 0) a = 1u;
+    else if (x == t) a = P16;
+    else if (in_row(O, D, t, x)) a = 65536u;
+    else a = Q16;
+    b[i] = w * a;
+  }
+}
+
+/* One walk, slots Y[0..L): start, then up to L-1 steps, then -1 padding.
+ * k_approx > 0: steps from nodes of degree > k_approx use the SUSS sub-sample. */
 static int32_t one_walk(const uint64_t* O, int64_t n, const int32_t* D, const uint32_t* W,
                         int32_t start, uint32_t L, int second_order,
-                        uint32_t P16, uint32_t Q16, uint64_t seed, uint64_t wid,
-                        uint64_t* b, int32_t* Y) {
+                        uint32_t P16, uint32_t Q16, uint64_t seed, uint64_t wid, uint32_t k_approx,
+                        uint32_t* pos, uint64_t* b, int32_t* Y) {
   for (uint32_t s = 0; s < L; ++s) Y[s] = -1;
   if (start < 0 || (int64_t)start >= n) return 0;
   Y[0] = start;
   int32_t len = 1;
   int32_t t = -1, v = start;
   for (uint32_t s = 1; s < L; ++s) {
-    int64_t d = n2vo_step_weights(O, D, W, t, v, second_order, P16, Q16, b);
+    int64_t d = (int64_t)(O[v + 1] - O[v]);
     if (d == 0) break; /* dead end */
+    int sub = k_approx > 0 && d > (int64_t)k_approx;
+    int64_t nc;
+    if (sub) {
+      n2vo_suss(seed, s, wid, (uint32_t)d, k_approx, pos);
+      sub_weights(O, D, W, t, v, second_order, P16, Q16, pos, k_approx, b);
+      nc = k_approx;
+    } else {
+      nc = n2vo_step_weights(O, D, W, t, v, second_order, P16, Q16, b);
+    }
     uint64_t total = 0;
-    for (int64_t j = 0; j < d; ++j) total += b[j];
+    for (int64_t j = 0; j < nc; ++j) total += b[j];
     if (total == 0) break; /* every candidate has weight zero */
     uint64_t T = n2vo_scale(n2vo_draw64(seed, s, wid), total);
-    int64_t j = n2vo_select(b, d, T);
-    int32_t x = D[O[v] + j];
+    int64_t j = n2vo_select(b, nc, T);
+    int32_t x = D[O[v] + (sub ? (uint64_t)pos[j] : (uint64_t)j)];
     Y[s] = x;
     len = (int32_t)s + 1;
     t = v;
@@ -169,11 +213,11 @@ static int32_t one_walk(const uint64_t* O, int64_t n, const int32_t* D, const ui
   return len;
 }
 
-int n2vo_walks_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
-                      const uint32_t* W, const int32_t* S, int64_t ns,
-                      uint32_t reps, uint32_t L, int kind, double p, double q,
-                      uint64_t seed, uint64_t walk_id_base,
-                      const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens) {
+int n2vo_walks_approx_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+                             const uint32_t* W, const int32_t* S, int64_t ns,
+                             uint32_t reps, uint32_t L, int kind, double p, double q,
+                             uint32_t k_approx, uint64_t seed, uint64_t walk_id_base,
+                             const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens) {
   if (n < 0 || ns < 0 || nw < 0 || L == 0 || reps == 0) return N2VO_ERR_INVALID_ARG;
   for (int64_t k = 0; k < nw; ++k)
     if (widx[k] < 0 || widx[k] >= ns * (int64_t)reps) return N2VO_ERR_INVALID_ARG;
@@ -195,20 +239,35 @@ int n2vo_walks_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m
   if ((unsigned __int128)max_sum * amax > (unsigned __int128)UINT64_MAX) return N2VO_ERR_OVERFLOW;
 
   uint64_t* b = (uint64_t*)0;
+  uint32_t* pos = (uint32_t*)malloc(sizeof(uint32_t) * (k_approx ? k_approx : 1));
+  if (!pos) return N2VO_ERR_INVALID_ARG;
   if (max_deg > 0) {
     b = (uint64_t*)malloc(sizeof(uint64_t) * max_deg);
-    if (!b) return N2VO_ERR_INVALID_ARG;
+    if (!b) {
+      free(pos);
+      return N2VO_ERR_INVALID_ARG;
+    }
   }
   (void)m;
   for (int64_t k = 0; k < nw; ++k) {
     int64_t w = widx[k];
     int32_t start = S[w % ns];
     int32_t len = one_walk(O, n, D, W, start, L, kind == N2VO_NODE2VEC, P16, Q16, seed,
-                           walk_id_base + (uint64_t)w, b, Y + (size_t)k * L);
+                           walk_id_base + (uint64_t)w, k_approx, pos, b, Y + (size_t)k * L);
     if (lens) lens[k] = len;
   }
   free(b);
+  free(pos);
   return N2VO_OK;
+}
+
+int n2vo_walks_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+                      const uint32_t* W, const int32_t* S, int64_t ns,
+                      uint32_t reps, uint32_t L, int kind, double p, double q,
+                      uint64_t seed, uint64_t walk_id_base,
+                      const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens) {
+  return n2vo_walks_approx_subset(O, n, D, m, W, S, ns, reps, L, kind, p, q, 0u, seed, walk_id_base,
+                                  widx, nw, Y, lens);
 }
 
 int n2vo_walks(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,

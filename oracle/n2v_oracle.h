@@ -88,6 +88,24 @@ int n2vo_walks_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m
                       uint64_t seed, uint64_t walk_id_base,
                       const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens);
 
+/* Sorted Unique Sub-Sampling (Methods, "Approximated RWs"): k sorted, unique
+ * positions in [0, d) for d > k.  The range is cut into k buckets of length
+ * floor(d / k), the last one also taking the remainder; bucket i gets the
+ * position start_i + floor(r64_i * len_i / 2^64), where r64_i is the 64-bit
+ * word pair (2 (i mod 2), 2 (i mod 2) + 1) of Philox4x32-10 under key seed and
+ * counter (step, wid lo, wid hi, 1 + floor(i / 2)). */
+void n2vo_suss(uint64_t seed, uint32_t step, uint64_t wid, uint32_t d, uint32_t k, uint32_t* pos);
+
+/* n2vo_walks_subset with approximated steps: a step from a node of degree
+ * d > k_approx considers only the SUSS sub-sample of k_approx neighbours
+ * (weights and search biases as in the exact step, normalised over the
+ * sub-sample); k_approx == 0 or d <= k_approx gives the exact step. */
+int n2vo_walks_approx_subset(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
+                             const uint32_t* W, const int32_t* S, int64_t ns,
+                             uint32_t reps, uint32_t L, int kind, double p, double q,
+                             uint32_t k_approx, uint64_t seed, uint64_t walk_id_base,
+                             const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens);
+
 /* All reps*ns walks, row w = rep*ns + i. */
 int n2vo_walks(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
                const uint32_t* W, const int32_t* S, int64_t ns,
