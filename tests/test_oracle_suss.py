@@ -133,3 +133,18 @@ def test_approximated_invariants():
             for s in range(1, int(lens[w])):
                 a, b = int(Y[w, s - 1]), int(Y[w, s])
                 assert b in set(int(x) for x in D[int(O[a]):int(O[a + 1])])
+
+
+def test_suss_buckets_independent():
+    """Offsets within adjacent buckets are independent (every bucket has its own
+    64-bit draw): chi-square of the joint offsets of buckets (0,1) and (1,2)."""
+    d, k, reps = 40, 8, 60_000  # buckets of 5
+    j01 = np.zeros((5, 5), dtype=np.int64)
+    j12 = np.zeros((5, 5), dtype=np.int64)
+    for r in range(reps):
+        pos = oracle.suss(9, 3, r, d, k).astype(np.int64)
+        off = pos - np.arange(k) * 5
+        j01[off[0], off[1]] += 1
+        j12[off[1], off[2]] += 1
+    for j in (j01, j12):
+        assert chisquare(j.ravel(), np.full(25, reps / 25)).pvalue > 1e-6
