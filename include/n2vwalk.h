@@ -142,6 +142,22 @@ int n2v_walks_node2vec(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
                        uint64_t seed, uint64_t walk_id_base, int32_t* d_walks,
                        int32_t* d_lens, void* hip_stream);
 
+/* Approximated walks (Methods, "Approximated RWs"): a step from a node of
+ * degree d > k considers only k of its neighbours, chosen by Sorted Unique
+ * Sub-Sampling: [0, d) is cut into k buckets of length floor(d / k), the last
+ * one also taking the remainder, and one position is drawn uniformly in each
+ * bucket (bucket i uses the 64-bit word pair (2 (i mod 2), 2 (i mod 2) + 1) of
+ * Philox4x32-10 with counter (step, walk id lo, walk id hi, 1 + floor(i / 2))).
+ * The step then samples among the k candidates exactly as an exact step does
+ * among all of N(v) (weights, search biases, cumulative sum, same draw).
+ * Steps from nodes of degree <= k are exact, so k >= max degree reproduces
+ * n2v_walks_first_order / n2v_walks_node2vec.  kind: N2V_FIRST_ORDER (p, q
+ * ignored) or N2V_NODE2VEC.  k == 0 is INVALID_ARG; otherwise as the plain calls. */
+int n2v_walks_approximated(n2v_graph g, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
+                           uint32_t walks_per_start, uint32_t walk_len, double p, double q,
+                           uint32_t k, uint64_t seed, uint64_t walk_id_base, int32_t* d_walks,
+                           int32_t* d_lens, void* hip_stream);
+
 /* Process-wide tuning override (NULL restores automatic tuning).  Used to
  * show that every tuning point yields identical walks. */
 int n2v_set_tuning(const n2v_tuning_t* tuning);
@@ -159,7 +175,7 @@ typedef struct {
   uint32_t kind;            /* N2V_FIRST_ORDER or N2V_NODE2VEC */
   uint32_t walks_per_start;
   uint32_t walk_len;
-  uint32_t reserved;
+  uint32_t k_approx;        /* 0: exact walks; k: approximated walks (see n2v_walks_approximated) */
   double p, q;              /* ignored for first order */
   uint64_t seed;
   uint64_t walk_id_base;

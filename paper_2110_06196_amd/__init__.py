@@ -53,7 +53,7 @@ class Tuning(ctypes.Structure):
 class RequestDesc(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_uint64), ("kind", ctypes.c_uint32),
                 ("walks_per_start", ctypes.c_uint32), ("walk_len", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("p", ctypes.c_double), ("q", ctypes.c_double),
+                ("k_approx", ctypes.c_uint32), ("p", ctypes.c_double), ("q", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("walk_id_base", ctypes.c_uint64),
                 ("d_starts", ctypes.c_void_p), ("n_starts", ctypes.c_uint64),
                 ("d_walks", ctypes.c_void_p), ("d_lens", ctypes.c_void_p)]
@@ -81,6 +81,7 @@ SIGNATURES = {
     "n2v_graph_release": [_U64],
     "n2v_walks_first_order": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP, _VP],
     "n2v_walks_node2vec": [_U64, _VP, _U64, _U32, _U32, _D, _D, _U64, _U64, _VP, _VP, _VP],
+    "n2v_walks_approximated": [_U64, _U32, _VP, _U64, _U32, _U32, _D, _D, _U32, _U64, _U64, _VP, _VP, _VP],
     "n2v_set_tuning": [ctypes.POINTER(Tuning)],
     "n2v_walks_batched": [ctypes.POINTER(RequestDesc), _U32, _VP],
     "n2v_batch_create": [ctypes.POINTER(RequestDesc), _U32, _U32, ctypes.POINTER(_U64)],
@@ -215,9 +216,20 @@ def n2v_walks_node2vec(g: int, starts, walks_per_start: int, walk_len: int, p: f
     return walks, lens
 
 
+def n2v_walks_approximated(g: int, kind: int, starts, walks_per_start: int, walk_len: int, p: float, q: float,
+                           k: int, seed: int, walk_id_base: int = 0, walks=None, lens=None, stream=None):
+    """Enqueue approximated walks (k sub-sampled neighbours per step from rows longer than k)."""
+    _dev(starts, torch.int32, "starts")
+    walks, lens = _alloc_out(starts, walks_per_start, walk_len, walks, lens)
+    _check(lib().n2v_walks_approximated(g, kind, _ptr(starts), starts.numel(), walks_per_start, walk_len,
+                                        float(p), float(q), k, seed, walk_id_base, _ptr(walks), _ptr(lens),
+                                        _stream(stream)))
+    return walks, lens
+
+
 def make_request(graph: int, kind: int, starts, walks_per_start: int, walk_len: int, p=1.0, q=1.0,
-                 seed=0, walk_id_base=0, walks=None, lens=None) -> RequestDesc:
-    return RequestDesc(graph, kind, walks_per_start, walk_len, 0, float(p), float(q), seed,
+                 seed=0, walk_id_base=0, walks=None, lens=None, k_approx: int = 0) -> RequestDesc:
+    return RequestDesc(graph, kind, walks_per_start, walk_len, k_approx, float(p), float(q), seed,
                        walk_id_base, starts.data_ptr() if starts is not None else None,
                        starts.numel() if starts is not None else 0,
                        walks.data_ptr() if walks is not None else None,
@@ -266,12 +278,12 @@ def n2v_server_add_graph(s: int, g: int) -> None:
 
 
 def host_request(graph: int, kind: int, starts_np, walks_per_start: int, walk_len: int, p=1.0, q=1.0,
-                 seed=0, walk_id_base=0):
+                 seed=0, walk_id_base=0, k_approx: int = 0):
     """A RequestDesc whose starts point at host memory (for n2v_request_submit).
     Returns (desc, keepalive): keep the second item alive until submit returns."""
     import numpy as np
     arr = np.ascontiguousarray(starts_np, dtype=np.int32)
-    d = RequestDesc(graph, kind, walks_per_start, walk_len, 0, float(p), float(q), seed, walk_id_base,
+    d = RequestDesc(graph, kind, walks_per_start, walk_len, k_approx, float(p), float(q), seed, walk_id_base,
                     arr.ctypes.data if arr.size else None, arr.size, None, None)
     return d, arr
 

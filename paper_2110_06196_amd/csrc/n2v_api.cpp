@@ -136,8 +136,8 @@ bool generic_only() {
 // Validate a walk request and fill the kernel arguments.
 int prepare_request(const GraphRec& gr, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
                     uint32_t walks_per_start, uint32_t walk_len, double p, double q, uint64_t seed,
-                    uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens, WalkArgs* a,
-                    Path* path) {
+                    uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens, uint32_t k_approx,
+                    WalkArgs* a, Path* path) {
   if (walk_len == 0) return fail(N2V_ERR_INVALID_ARG, "walk_len must be >= 1");
   if (walks_per_start == 0) return fail(N2V_ERR_INVALID_ARG, "walks_per_start must be >= 1");
   if (kind != N2V_FIRST_ORDER && kind != N2V_NODE2VEC) return fail(N2V_ERR_INVALID_ARG, "bad kind");
@@ -171,14 +171,15 @@ int prepare_request(const GraphRec& gr, uint32_t kind, const int32_t* d_starts, 
   // Variant dispatch (the paper's eight specialisations): first order and
   // node2vec with p = q = 1 share the first-order kernels; node2vec with
   // 1/q == 1 only re-weights the return edge; everything else is generic.
-  if (generic_only()) *path = Path::kGeneric;
+  // Approximated walks (sub-sampled rows) always run on the G-lanes kernel.
+  if (generic_only() || k_approx > 0) *path = Path::kGeneric;
   else if (kind == N2V_FIRST_ORDER || (P16 == kC16Host && Q16 == kC16Host)) {
     *path = Path::kFirstOrder;
     a->second_order = 0;
   } else if (Q16 == kC16Host) *path = Path::kReturnOnly;
   else *path = Path::kGeneric;
   a->path = (uint32_t)*path;
-  a->pad = 0;
+  a->k_approx = k_approx;
   a->steps = nullptr;
   return N2V_OK;
 }
@@ -310,13 +311,13 @@ int n2v_set_tuning(const n2v_tuning_t* tuning) {
 static int walks_common(n2v_graph g, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
                         uint32_t walks_per_start, uint32_t walk_len, double p, double q,
                         uint64_t seed, uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens,
-                        void* hip_stream) {
+                        uint32_t k_approx, void* hip_stream) {
   GraphRec* gr = find_graph(g);
   if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
   WalkArgs a;
   Path path;
   int rc = prepare_request(*gr, kind, d_starts, n_starts, walks_per_start, walk_len, p, q, seed,
-                           walk_id_base, d_walks, d_lens, &a, &path);
+                           walk_id_base, d_walks, d_lens, k_approx, &a, &path);
   if (rc != N2V_OK) return rc;
   if (a.nwalks == 0) return N2V_OK;
   DevInfo di;
@@ -333,7 +334,7 @@ int n2v_walks_first_order(n2v_graph g, const int32_t* d_starts, uint64_t n_start
                           uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens,
                           void* hip_stream) {
   return walks_common(g, N2V_FIRST_ORDER, d_starts, n_starts, walks_per_start, walk_len, 1.0, 1.0,
-                      seed, walk_id_base, d_walks, d_lens, hip_stream);
+                      seed, walk_id_base, d_walks, d_lens, 0u, hip_stream);
 }
 
 int n2v_walks_node2vec(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
@@ -341,7 +342,16 @@ int n2v_walks_node2vec(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
                        uint64_t seed, uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens,
                        void* hip_stream) {
   return walks_common(g, N2V_NODE2VEC, d_starts, n_starts, walks_per_start, walk_len, p, q, seed,
-                      walk_id_base, d_walks, d_lens, hip_stream);
+                      walk_id_base, d_walks, d_lens, 0u, hip_stream);
+}
+
+int n2v_walks_approximated(n2v_graph g, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
+                           uint32_t walks_per_start, uint32_t walk_len, double p, double q,
+                           uint32_t k, uint64_t seed, uint64_t walk_id_base, int32_t* d_walks,
+                           int32_t* d_lens, void* hip_stream) {
+  if (k == 0) return fail(N2V_ERR_INVALID_ARG, "k must be >= 1");
+  return walks_common(g, kind, d_starts, n_starts, walks_per_start, walk_len, p, q, seed, walk_id_base,
+                      d_walks, d_lens, k, hip_stream);
 }
 
 }  // extern "C"

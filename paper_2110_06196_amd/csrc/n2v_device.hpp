@@ -13,6 +13,30 @@ constexpr uint32_t kC16 = 65536u;  // alpha = 1 (common neighbour) in Q16
 // multiply-xor bijection with the key advanced by the Weyl constants between
 // rounds.  Key = (seed lo, seed hi), counter = (step, wid lo, wid hi, 0); the
 // 64-bit draw is word0 | word1 << 32.
+__device__ __forceinline__ void philox_words(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t out[4]) {
+  uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t lo0 = m0 * x0, hi0 = __umulhi(m0, x0);
+    uint32_t lo1 = m1 * x2, hi1 = __umulhi(m1, x2);
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
 __device__ __forceinline__ uint64_t philox_draw(uint64_t seed, uint32_t step, uint64_t wid) {
   uint32_t x0 = step, x1 = (uint32_t)wid, x2 = (uint32_t)(wid >> 32), x3 = 0u;
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);

@@ -38,8 +38,8 @@ struct WalkArgs {
   uint64_t wid_base;
   int32_t* Y;
   int32_t* lens;
-  uint32_t path;  // Path, used by the batched kernel
-  uint32_t pad;
+  uint32_t path;      // Path, used by the batched kernel
+  uint32_t k_approx;  // 0: exact steps; k: steps from rows longer than k use k sub-sampled neighbours
   unsigned long long* steps;  // if non-null: += sum over walks of (len - 1)
 };
 

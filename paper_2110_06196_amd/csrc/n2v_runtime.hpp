@@ -33,7 +33,7 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di);
 void apply_tuning_override(LaunchCfg* c, const DevInfo& di);
 int prepare_request(const GraphRec& gr, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
                     uint32_t walks_per_start, uint32_t walk_len, double p, double q, uint64_t seed,
-                    uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens, WalkArgs* a,
-                    Path* path);
+                    uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens, uint32_t k_approx,
+                    WalkArgs* a, Path* path);
 
 }  // namespace n2v

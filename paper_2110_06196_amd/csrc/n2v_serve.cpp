@@ -56,7 +56,7 @@ int prepare_all(const n2v_request_desc_t* reqs, uint32_t n, std::vector<Prepared
     Prepared p;
     Path path;
     int rc = prepare_request(*gr, r.kind, r.d_starts, r.n_starts, r.walks_per_start, r.walk_len, r.p,
-                             r.q, r.seed, r.walk_id_base, r.d_walks, r.d_lens, &p.args, &path);
+                             r.q, r.seed, r.walk_id_base, r.d_walks, r.d_lens, r.k_approx, &p.args, &path);
     if (rc != N2V_OK) return fail(rc, "request %u: %s", i, t_err.c_str());
     p.walk_cost = (double)(r.walk_len > 1 ? r.walk_len - 1 : 1) * step_cost(*gr, path);
     out->push_back(p);
@@ -335,7 +335,7 @@ void admit_locked(Server* s) {
     if (rc == N2V_OK)
       rc = prepare_request(*r->gr, d.kind, (const int32_t*)((uint8_t*)r->mem + off_s), d.n_starts,
                            d.walks_per_start, d.walk_len, d.p, d.q, d.seed, d.walk_id_base,
-                           (int32_t*)r->mem, (int32_t*)((uint8_t*)r->mem + off_l), &r->args, &path);
+                           (int32_t*)r->mem, (int32_t*)((uint8_t*)r->mem + off_l), d.k_approx, &r->args, &path);
     if (rc != N2V_OK) {
       r->state = RState::kFailed;
       r->err = rc;
@@ -719,7 +719,7 @@ int n2v_request_submit(n2v_server sh, const n2v_request_desc_t* desc, uint64_t a
     Path path;
     int32_t dummy = 0;
     int rc = prepare_request(*gr, desc->kind, &dummy, 0, desc->walks_per_start, desc->walk_len, desc->p, desc->q,
-                             desc->seed, desc->walk_id_base, &dummy, nullptr, &a, &path);
+                             desc->seed, desc->walk_id_base, &dummy, nullptr, desc->k_approx, &a, &path);
     if (rc != N2V_OK) return rc;
   }
   SrvReq* r = new SrvReq();

@@ -314,7 +314,74 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           }
         };
 
-        if (!a.second_order || t < 0) {
+        // Approximated step (Methods, "Approximated RWs"): only the Sorted
+        // Unique Sub-Sample of k neighbours is considered, one uniform position
+        // per bucket of length floor(d / k) (the last bucket takes the
+        // remainder); the biased weights are normalised over the sub-sample.
+        auto approx_step = [&]() {
+          const uint32_t k = a.k_approx;
+          const uint32_t blen = d / k;
+          auto pos_of = [&](uint32_t i) -> uint32_t {
+            uint32_t o[4];
+            philox_words(a.seed, s, (uint32_t)wid, (uint32_t)(wid >> 32), 1u + i / 2u, o);
+            const uint64_t rr = (i & 1u) ? ((uint64_t)o[2] | ((uint64_t)o[3] << 32))
+                                         : ((uint64_t)o[0] | ((uint64_t)o[1] << 32));
+            const uint32_t st = i * blen;
+            const uint32_t ln = (i + 1 < k) ? blen : d - st;
+            return st + (uint32_t)scale_draw(rr, ln);
+          };
+          const bool second = a.second_order && t >= 0;
+          auto weight = [&](uint32_t p) -> uint64_t {
+            const int32_t x = D[lo + p];
+            const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + p] : 1ull;
+            if (!second) return wt;
+            if (x == t) return wt * P16;
+            return wt * (member(x) ? (uint64_t)kC16 : Q16);
+          };
+          const uint32_t nc = (k + G - 1) / G;
+          const uint32_t bs = (nc + G - 1) / G;
+          uint64_t acc = 0, blk = 0;
+          for (uint32_t c = 0; c < nc; ++c) {
+            const uint32_t i = c * G + gl;
+            if (i < k) acc += weight(pos_of(i));
+            if ((c + 1) % bs == 0 || c + 1 == nc) {
+              const uint64_t sb = grp_sum<G>(acc);
+              if ((uint32_t)gl == c / bs) blk = sb;
+              acc = 0;
+            }
+          }
+          const uint64_t incl = grp_incl_scan<G>(blk, gl);
+          const uint64_t total = grp_bcast<G>(incl, G - 1);
+          if (total == 0) {
+            stop = true;
+            return;
+          }
+          const uint64_t T = scale_draw(r, total);
+          const uint64_t bm = grp_ballot<G>(incl > T, gbase);
+          const int kb = __ffsll((unsigned long long)bm) - 1;
+          uint64_t base = grp_bcast<G>(incl - blk, kb);
+          const uint32_t cend = min((uint32_t)(kb + 1) * bs, nc);
+          for (uint32_t c = (uint32_t)kb * bs; c < cend; ++c) {
+            const uint32_t i = c * G + gl;
+            uint64_t b = 0;
+            uint32_t p = 0;
+            if (i < k) {
+              p = pos_of(i);
+              b = weight(p);
+            }
+            const uint64_t inc = grp_incl_scan<G>(b, gl);
+            const uint64_t m2 = grp_ballot<G>(base + inc > T, gbase);
+            if (m2) {
+              jsel = (uint32_t)grp_bcast_i32<G>((int32_t)p, __ffsll((unsigned long long)m2) - 1);
+              break;
+            }
+            base += grp_bcast<G>(inc, G - 1);
+          }
+        };
+
+        if (a.k_approx != 0 && d > a.k_approx) {
+          approx_step();
+        } else if (!a.second_order || t < 0) {
           // First-order step (also the first step of a node2vec walk).
           if (S == 0) break;
           const uint64_t T = scale_draw(r, S);
