@@ -51,6 +51,7 @@ def parse():
                          "launch per request vs one persistent hipGraph launch; served: the same requests "
                          "under Poisson arrivals, server vs one launch per request")
     ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (req/s)")
+    ap.add_argument("--approx-k", default="100,10", help="big: sub-sample sizes of approximated node2vec runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (PMC counter calibration)")
     ap.add_argument("--summarize-profiles", nargs=7, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
@@ -700,12 +701,16 @@ def bench_big(args):
     host = (O.cpu().numpy().view(np.uint64), D.cpu().numpy(), W.cpu().numpy().view(np.uint32))
     rows = np.linspace(0, n - 1, 300).astype(np.int64)
     runs = []
-    for kind, p, q in [(n2v.N2V_FIRST_ORDER, 1.0, 1.0), (n2v.N2V_NODE2VEC, 1.0, 2.0)]:
+    plan = [(n2v.N2V_FIRST_ORDER, 1.0, 1.0, 0), (n2v.N2V_NODE2VEC, 1.0, 2.0, 0)]
+    plan += [(n2v.N2V_NODE2VEC, 1.0, 2.0, int(k)) for k in args.approx_k.split(",") if k]
+    for kind, p, q, ka in plan:
         ms = []
         for k in range(args.warmup + args.steps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            if kind == n2v.N2V_FIRST_ORDER:
+            if ka:
+                n2v.n2v_walks_approximated(g, kind, S, 1, L, p, q, ka, 42, 0, Y, lens)
+            elif kind == n2v.N2V_FIRST_ORDER:
                 n2v.n2v_walks_first_order(g, S, 1, L, 42, 0, Y, lens)
             else:
                 n2v.n2v_walks_node2vec(g, S, 1, L, p, q, 42, 0, Y, lens)
@@ -713,24 +718,25 @@ def bench_big(args):
             torch.cuda.synchronize()
             if k >= args.warmup:
                 ms.append(e0.elapsed_time(e1))
-            print(f"[bench] kind {kind} p {p} q {q} launch {k}: {e0.elapsed_time(e1):.1f} ms", file=sys.stderr,
-                  flush=True)
+            print(f"[bench] kind {kind} p {p} q {q} k {ka} launch {k}: {e0.elapsed_time(e1):.1f} ms",
+                  file=sys.stderr, flush=True)
         steps = int((lens.to(torch.int64) - 1).clamp(min=0).sum().item())
         idx = torch.from_numpy(rows).to(dev)
         Yg = Y.index_select(0, idx).cpu().numpy()
         lg = lens.index_select(0, idx).cpu().numpy()
         t1 = time.perf_counter()
-        Yo, lo = oracle.walks_threaded(*host, S.cpu().numpy(), 1, L, kind, p, q, 42, 0, rows, min(16, os.cpu_count()))
+        Yo, lo = oracle.walks_threaded(*host, S.cpu().numpy(), 1, L, kind, p, q, 42, 0, rows, min(16, os.cpu_count()),
+                                       k_approx=ka)
         ct = time.perf_counter() - t1
         csteps = int(np.maximum(lo.astype(np.int64) - 1, 0).sum())
-        runs.append({"kind": "first_order" if kind == 0 else "node2vec", "p": p, "q": q,
+        runs.append({"kind": "first_order" if kind == 0 else "node2vec", "p": p, "q": q, "k_approx": ka,
                      "mean_ms": float(np.mean(ms)), "steps": steps, "steps_per_s": steps / (np.mean(ms) / 1e3),
                      "oracle_sample_mismatching_rows": int(((Yg != Yo).any(1) | (lg != lo)).sum()),
                      "oracle_steps_per_s": csteps / ct})
     out = {"metric": METRIC, "value": runs[1]["steps_per_s"], "unit": "walk steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": runs[1]["mean_ms"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-           "config": {"workload": "plain first-order and node2vec (p=1, q=2) on a Chung-Lu graph: 20M nodes, 1e9 "
+           "config": {"workload": "plain first-order, node2vec (p=1, q=2) and approximated node2vec on a Chung-Lu graph: 20M nodes, 1e9 "
                                   "undirected edge samples (gamma 2.2, max expected degree 2e6), weights U[1,255], "
                                   "one walk of 80 slots per node, seed 42",
                       "n_entries": int(D.numel()), "max_degree": info["max_degree"],
