@@ -85,6 +85,12 @@ def lib():
             L.n2vo_walks_approx_subset.argtypes = (common[:12] + [ctypes.c_uint32] + common[12:] +
                                                    [i64p, ctypes.c_int64, i32p, i32p])
             L.n2vo_walks_approx_subset.restype = ctypes.c_int
+            L.n2vo_contexts.argtypes = [i32p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                        i32p]
+            L.n2vo_contexts.restype = None
+            L.n2vo_negatives.argtypes = [u64p, ctypes.c_int64, i32p, ctypes.c_int64, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, i32p]
+            L.n2vo_negatives.restype = None
             _lib = L
     return _lib
 
@@ -224,3 +230,23 @@ def walks_threaded(offsets, dst, weights, starts, walks_per_start, walk_len, kin
     Y = np.concatenate([o[0] for o in out]) if out else np.empty((0, walk_len), np.int32)
     lens = np.concatenate([o[1] for o in out]) if out else np.empty(0, np.int32)
     return Y, lens
+
+
+def contexts(Y, window: int, stride: int = 1):
+    """Context slots [nw][L][2 window] of every walk position (see n2v_oracle.h)."""
+    Yc = np.ascontiguousarray(Y, dtype=np.int32)
+    nw, L = Yc.shape
+    C = np.empty((nw, L, 2 * window), dtype=np.int32)
+    lib().n2vo_contexts(_p(Yc, ctypes.c_int32), nw, L, window, stride, _p(C, ctypes.c_int32))
+    return C
+
+
+def negatives(offsets, Y, n_neg: int, seed: int, walk_id_base: int = 0):
+    """Scale-free negatives [nw][L][n_neg] (see n2v_oracle.h)."""
+    O = np.ascontiguousarray(offsets, dtype=np.uint64)
+    Yc = np.ascontiguousarray(Y, dtype=np.int32)
+    nw, L = Yc.shape
+    N = np.empty((nw, L, n_neg), dtype=np.int32)
+    lib().n2vo_negatives(_p(O, ctypes.c_uint64), O.size - 1, _p(Yc, ctypes.c_int32), nw, L, n_neg, seed,
+                         walk_id_base, _p(N, ctypes.c_int32))
+    return N

@@ -284,3 +284,52 @@ int n2vo_walks(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
   free(widx);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Training contexts and scale-free negatives.                               */
+/* ------------------------------------------------------------------------ */
+void n2vo_contexts(const int32_t* Y, int64_t nw, uint32_t L, uint32_t window, uint32_t stride, int32_t* C) {
+  for (int64_t r = 0; r < nw; ++r) {
+    for (uint32_t i = 0; i < L; ++i) {
+      int32_t* out = C + ((size_t)r * L + i) * 2 * window;
+      for (uint32_t c = 0; c < 2 * window; ++c) {
+        int64_t o = c < window ? (int64_t)c - (int64_t)window : (int64_t)c - (int64_t)window + 1;
+        int64_t j = (int64_t)i + o * (int64_t)stride;
+        int32_t v = -1;
+        if (Y[(size_t)r * L + i] >= 0 && j >= 0 && j < (int64_t)L) v = Y[(size_t)r * L + j];
+        out[c] = v;
+      }
+    }
+  }
+}
+
+void n2vo_negatives(const uint64_t* O, int64_t n, const int32_t* Y, int64_t nw, uint32_t L, uint32_t n_neg,
+                    uint64_t seed, uint64_t walk_id_base, int32_t* N) {
+  uint64_t m = O[n];
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int64_t r = 0; r < nw; ++r) {
+    uint64_t wid = walk_id_base + (uint64_t)r;
+    for (uint32_t i = 0; i < L; ++i) {
+      int32_t* out = N + ((size_t)r * L + i) * n_neg;
+      for (uint32_t j = 0; j < n_neg; ++j) {
+        int32_t v = -1;
+        if (Y[(size_t)r * L + i] >= 0 && m > 0) {
+          uint32_t ctr[4] = {i, (uint32_t)wid, (uint32_t)(wid >> 32), 0x80000000u + j / 2u};
+          uint32_t o[4];
+          n2vo_philox4x32_10(ctr, key, o);
+          uint64_t r64 = (uint64_t)o[2 * (j % 2)] | ((uint64_t)o[2 * (j % 2) + 1] << 32);
+          uint64_t T = n2vo_scale(r64, m);
+          /* the node whose range of entries [O[v], O[v+1]) holds T: plain scan */
+          int64_t lo = 0, hi = n; /* O[lo] <= T < O[hi] */
+          while (hi - lo > 1) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (O[mid] <= T) lo = mid;
+            else hi = mid;
+          }
+          v = (int32_t)lo;
+        }
+        out[j] = v;
+      }
+    }
+  }
+}

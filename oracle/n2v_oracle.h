@@ -106,6 +106,23 @@ int n2vo_walks_approx_subset(const uint64_t* O, int64_t n, const int32_t* D, uin
                              uint32_t k_approx, uint64_t seed, uint64_t walk_id_base,
                              const int64_t* widx, int64_t nw, int32_t* Y, int32_t* lens);
 
+/* Training contexts of every walk position (Methods, "First and second-order
+ * RW-based embedding methods": window-based SkipGram / CBOW corpora; with a
+ * stride k the Walklets corpus of scale k).  For walk row r and centre i
+ * (Y[r][i] >= 0), slot c in [0, 2 window) holds Y[r][i + o * stride] with
+ * o = c - window for c < window and o = c - window + 1 otherwise, or -1 when
+ * that position is outside the walk or unused (-1).  C is [nw][L][2 window]. */
+void n2vo_contexts(const int32_t* Y, int64_t nw, uint32_t L, uint32_t window, uint32_t stride, int32_t* C);
+
+/* Scale-free negatives: for walk row r (walk id walk_id_base + r) and centre i
+ * with Y[r][i] >= 0, N[r][i][j] (j < n_neg) is the node v with
+ * O[v] <= T < O[v+1], T = floor(r64 * m / 2^64), i.e. a node drawn with
+ * probability proportional to its out-degree; r64 is the word pair
+ * (2 (j mod 2), 2 (j mod 2) + 1) of Philox4x32-10 under key seed and counter
+ * (i, wid lo, wid hi, 2^31 + floor(j / 2)).  Other slots hold -1. */
+void n2vo_negatives(const uint64_t* O, int64_t n, const int32_t* Y, int64_t nw, uint32_t L, uint32_t n_neg,
+                    uint64_t seed, uint64_t walk_id_base, int32_t* N);
+
 /* All reps*ns walks, row w = rep*ns + i. */
 int n2vo_walks(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
                const uint32_t* W, const int32_t* S, int64_t ns,
