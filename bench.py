@@ -46,12 +46,15 @@ def parse():
     ap.add_argument("--runs", default="1,1;0.25,4", help="(p,q) pairs, ';'-separated")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--walk-len", type=int, default=100)
-    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served", "big"],
+    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served", "big", "corpus"],
                     help="chung_lu_1m: plain launches (default); batched: 64 graphs x 4096 requests, one "
                          "launch per request vs one persistent hipGraph launch; served: the same requests "
                          "under Poisson arrivals, server vs one launch per request")
     ap.add_argument("--rates", default="200,1000,5000", help="served: arrival rates (req/s)")
     ap.add_argument("--approx-k", default="100,10", help="big: sub-sample sizes of approximated node2vec runs")
+    ap.add_argument("--window", type=int, default=5, help="corpus: SkipGram / CBOW window")
+    ap.add_argument("--walklets", default="2,4", help="corpus: Walklets scales")
+    ap.add_argument("--negatives", type=int, default=5, help="corpus: negatives per walk position")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (PMC counter calibration)")
     ap.add_argument("--summarize-profiles", nargs=7, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
@@ -279,6 +282,9 @@ def main():
         return
     if args.config == "big":
         bench_big(args)
+        return
+    if args.config == "corpus":
+        bench_corpus(args)
         return
     import torch
     import paper_2110_06196_amd as n2v
@@ -742,6 +748,101 @@ def bench_big(args):
                       "n_entries": int(D.numel()), "max_degree": info["max_degree"],
                       "stationary_mean_degree": info["sum_deg_sq"] / max(1, info["n_entries"])},
            "runs": runs, "kernel_source_hash": kernel_source_hash()}
+    print(json.dumps(out), flush=True)
+    n2v.n2v_graph_release(g)
+
+
+def bench_corpus(args):
+    """Training corpora of the 1M-node workload's walks (node2vec p=q=1, 10 walks
+    per node, 100 slots, seed 42): SkipGram / CBOW context slots of one window,
+    Walklets slots of each scale, and scale-free negatives per position.  One
+    step runs every corpus kernel once over all 1e9 walk positions; the walks
+    are generated once, before timing.  Sampled rows are checked against the
+    oracle, which is also timed on them."""
+    import torch
+    import oracle
+    import paper_2110_06196_amd as n2v
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    O, D, W = graph_cache()
+    n = len(O) - 1
+    Ot = torch.from_numpy(O.view(np.int64)).to(dev)
+    Dt = torch.from_numpy(D).to(dev)
+    Wt = torch.from_numpy(W.view(np.int32)).to(dev)
+    g = n2v.n2v_graph_upload(Ot, Dt, Wt)
+    R, L, seed = args.reps, args.walk_len, 42
+    nw = n * R
+    S = torch.arange(n, dtype=torch.int32, device=dev)
+    Y = torch.empty((nw, L), dtype=torch.int32, device=dev)
+    lens = torch.empty(nw, dtype=torch.int32, device=dev)
+    n2v.n2v_walks_node2vec(g, S, R, L, 1.0, 1.0, seed, 0, Y, lens)
+    torch.cuda.synchronize()
+    w, n_neg = args.window, args.negatives
+    scales = [int(k) for k in args.walklets.split(",") if k]
+    C = torch.empty((nw, L, 2 * w), dtype=torch.int32, device=dev)
+    Cw = [torch.empty((nw, L, 2), dtype=torch.int32, device=dev) for _ in scales]
+    N = torch.empty((nw, L, n_neg), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    npos = nw * L
+    ops = [(f"skipgram_window{w}", lambda: n2v.n2v_walk_contexts(Y, w, 1, C, stream=stream), npos * (4 + 8 * w))]
+    for k, buf in zip(scales, Cw):
+        ops.append((f"walklets_scale{k}", lambda k=k, buf=buf: n2v.n2v_walk_contexts(Y, 1, k, buf, stream=stream),
+                    npos * (4 + 8)))
+    ops.append((f"negatives{n_neg}", lambda: n2v.n2v_negative_samples(g, Y, n_neg, seed, 0, N, stream=stream),
+                npos * (4 + 4 * n_neg)))
+    print(f"[bench] corpus: {npos} walk positions, {len(ops)} kernels", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        for _, f, _ in ops:
+            f()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ops]
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for i, (_, f, _) in enumerate(ops):
+            ev[k][i][0].record(stream)
+            f()
+            ev[k][i][1].record(stream)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {tt:.3f}s", file=sys.stderr, flush=True)
+    kernels = []
+    for i, (name, _, alg) in enumerate(ops):
+        ms = float(np.mean([ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)]))
+        kernels.append({"op": name, "mean_ms": ms, "alg_bytes": alg, "alg_GBps": alg / (ms / 1e3) / 1e9,
+                        "positions_per_s": npos / (ms / 1e3)})
+    dom = max(kernels, key=lambda k: k["mean_ms"])
+
+    # Oracle on a contiguous block of walk rows (walk ids follow the row index).
+    rows = max(1, min(nw, int(20000 * max(args.cpu_seconds, 1.0) / 15.0)))
+    r0 = nw // 2 - rows // 2
+    Yh = Y[r0:r0 + rows].cpu().numpy()
+    mism = {}
+    t1 = time.perf_counter()
+    Co = oracle.contexts(Yh, w, 1)
+    Cwo = [oracle.contexts(Yh, 1, k) for k in scales]
+    No = oracle.negatives(O, Yh, n_neg, seed, r0)
+    ct = time.perf_counter() - t1
+    mism[kernels[0]["op"]] = int((C[r0:r0 + rows].cpu().numpy() != Co).any(axis=(1, 2)).sum())
+    for k, buf, ref in zip(scales, Cw, Cwo):
+        mism[f"walklets_scale{k}"] = int((buf[r0:r0 + rows].cpu().numpy() != ref).any(axis=(1, 2)).sum())
+    mism[kernels[-1]["op"]] = int((N[r0:r0 + rows].cpu().numpy() != No).any(axis=(1, 2)).sum())
+    ms_step = tt / args.steps * 1e3
+    out = {"metric": "walk positions turned into training corpora per second", "value": npos / (ms_step / 1e3),
+           "unit": "walk positions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64", "data": "synthetic",
+           "config": {"workload": f"corpora of the walks of node2vec p=q=1 on the Chung-Lu 1M-node graph, {R} walks "
+                                  f"per node, {L} slots, seed 42: SkipGram/CBOW window {w}, Walklets scales "
+                                  f"{scales}, {n_neg} scale-free negatives per position",
+                      "positions": npos},
+           "roofline": {"bound": "hbm", "achieved": dom["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": dom["alg_GBps"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom["op"]},
+           "cpu_baseline": {"value": rows * L / ct, "unit": "walk positions/s", "cores": 1, "kind": "oracle",
+                            "sample": f"walk rows [{r0}, {r0 + rows}) through every corpus op ({ct:.1f} s wall)"},
+           "kernels": kernels, "parity_sample": {"rows": rows, "mismatching_rows": mism},
+           "kernel_source_hash": kernel_source_hash()}
     print(json.dumps(out), flush=True)
     n2v.n2v_graph_release(g)
 

@@ -158,6 +158,33 @@ int n2v_walks_approximated(n2v_graph g, uint32_t kind, const int32_t* d_starts, 
                            uint32_t k, uint64_t seed, uint64_t walk_id_base, int32_t* d_walks,
                            int32_t* d_lens, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Training corpora from walks (the walks feed SkipGram / CBOW / GloVe models
+ * trained on sliding windows, Methods "First and second-order RW-based
+ * embedding methods"; Walklets uses skip distances).
+ *
+ * n2v_walk_contexts: d_walks int32[n_walks][walk_len] (as produced above, -1
+ * padded); d_contexts int32[n_walks][walk_len][2 window] receives, for every
+ * position i holding a node, the nodes at positions i + o * stride for
+ * o = -window .. -1, 1 .. window (slot c <-> o = c - window for c < window,
+ * c - window + 1 otherwise), or -1 outside the walk; positions without a node
+ * get -1 everywhere.  stride 1: SkipGram / CBOW windows; window 1 and stride k:
+ * the Walklets pairs of scale k.  Enqueued on hip_stream.
+ *
+ * n2v_negative_samples: d_negatives int32[n_walks][walk_len][n_neg]; for every
+ * position i of walk row r holding a node, n_neg nodes drawn with probability
+ * proportional to their out-degree ("scale-free negative sampling"): node v
+ * with offsets[v] <= T < offsets[v+1], T = floor(r64 * n_entries / 2^64), r64
+ * the word pair (2 (j mod 2), 2 (j mod 2) + 1) of Philox4x32-10 under key seed
+ * and counter (i, wid lo, wid hi, 2^31 + floor(j / 2)) with wid =
+ * walk_id_base + r.  Other slots get -1.  Enqueued on hip_stream.
+ * ------------------------------------------------------------------------- */
+int n2v_walk_contexts(const int32_t* d_walks, uint64_t n_walks, uint32_t walk_len, uint32_t window,
+                      uint32_t stride, int32_t* d_contexts, void* hip_stream);
+int n2v_negative_samples(n2v_graph g, const int32_t* d_walks, uint64_t n_walks, uint32_t walk_len,
+                         uint32_t n_neg, uint64_t seed, uint64_t walk_id_base, int32_t* d_negatives,
+                         void* hip_stream);
+
 /* Process-wide tuning override (NULL restores automatic tuning).  Used to
  * show that every tuning point yields identical walks. */
 int n2v_set_tuning(const n2v_tuning_t* tuning);

@@ -82,6 +82,8 @@ SIGNATURES = {
     "n2v_walks_first_order": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP, _VP],
     "n2v_walks_node2vec": [_U64, _VP, _U64, _U32, _U32, _D, _D, _U64, _U64, _VP, _VP, _VP],
     "n2v_walks_approximated": [_U64, _U32, _VP, _U64, _U32, _U32, _D, _D, _U32, _U64, _U64, _VP, _VP, _VP],
+    "n2v_walk_contexts": [_VP, _U64, _U32, _U32, _U32, _VP, _VP],
+    "n2v_negative_samples": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP],
     "n2v_set_tuning": [ctypes.POINTER(Tuning)],
     "n2v_walks_batched": [ctypes.POINTER(RequestDesc), _U32, _VP],
     "n2v_batch_create": [ctypes.POINTER(RequestDesc), _U32, _U32, ctypes.POINTER(_U64)],
@@ -98,6 +100,7 @@ SIGNATURES = {
 }
 
 _lib = None
+_borrowed: dict = {}  # graph handle -> the device tensors the library reads
 _lock = threading.Lock()
 
 
@@ -157,6 +160,9 @@ def n2v_graph_upload(offsets, dst, weights=None, stream=None) -> int:
     h = ctypes.c_uint64(0)
     _check(lib().n2v_graph_upload(_ptr(offsets), offsets.numel() - 1, _ptr(dst), dst.numel(),
                                   _ptr(weights), 0, _stream(stream), ctypes.byref(h)))
+    # The library reads these arrays until release: hold them so that the
+    # caching allocator cannot hand their memory to another tensor meanwhile.
+    _borrowed[h.value] = (offsets, dst, weights)
     return h.value
 
 
@@ -168,6 +174,7 @@ def n2v_graph_info(g: int) -> dict:
 
 def n2v_graph_release(g: int) -> None:
     _check(lib().n2v_graph_release(g))
+    _borrowed.pop(g, None)
 
 
 def n2v_set_tuning(lanes_per_walker=0, lds_tile=0, list_cap=0, route=0, flags=0, reset=False) -> None:
@@ -225,6 +232,29 @@ def n2v_walks_approximated(g: int, kind: int, starts, walks_per_start: int, walk
                                         float(p), float(q), k, seed, walk_id_base, _ptr(walks), _ptr(lens),
                                         _stream(stream)))
     return walks, lens
+
+
+def n2v_walk_contexts(walks, window: int, stride: int = 1, contexts=None, stream=None):
+    """Context slots int32[n_walks][walk_len][2 window] of every walk position."""
+    _dev(walks, torch.int32, "walks")
+    nw, L = walks.shape
+    if contexts is None:
+        contexts = torch.empty((nw, L, 2 * window), dtype=torch.int32, device=walks.device)
+    _dev(contexts, torch.int32, "contexts")
+    _check(lib().n2v_walk_contexts(_ptr(walks), nw, L, window, stride, _ptr(contexts), _stream(stream)))
+    return contexts
+
+
+def n2v_negative_samples(g: int, walks, n_neg: int, seed: int, walk_id_base: int = 0, negatives=None, stream=None):
+    """Degree-proportional negatives int32[n_walks][walk_len][n_neg] for every walk position."""
+    _dev(walks, torch.int32, "walks")
+    nw, L = walks.shape
+    if negatives is None:
+        negatives = torch.empty((nw, L, n_neg), dtype=torch.int32, device=walks.device)
+    _dev(negatives, torch.int32, "negatives")
+    _check(lib().n2v_negative_samples(g, _ptr(walks), nw, L, n_neg, seed, walk_id_base, _ptr(negatives),
+                                      _stream(stream)))
+    return negatives
 
 
 def make_request(graph: int, kind: int, starts, walks_per_start: int, walk_len: int, p=1.0, q=1.0,

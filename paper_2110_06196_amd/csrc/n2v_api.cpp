@@ -288,8 +288,67 @@ int n2v_graph_release(n2v_graph g) {
     g_graphs.erase(it);
   }
   if (gr->dev.R) hipFree(const_cast<void*>(gr->dev.R));
+  if (gr->neg_guide) hipFree(gr->neg_guide);
   delete gr;
   return N2V_OK;
+}
+
+int n2v_walk_contexts(const int32_t* d_walks, uint64_t n_walks, uint32_t walk_len, uint32_t window,
+                      uint32_t stride, int32_t* d_contexts, void* hip_stream) {
+  if (walk_len == 0 || window == 0 || stride == 0) return fail(N2V_ERR_INVALID_ARG, "walk_len, window and stride must be >= 1");
+  if (window > kMaxWindow) return fail(N2V_ERR_INVALID_ARG, "window %u above %u", window, kMaxWindow);
+  if (n_walks > 0 && (!d_walks || !d_contexts)) return fail(N2V_ERR_INVALID_ARG, "walks and contexts must be non-NULL");
+  if ((unsigned __int128)n_walks * walk_len * window >= ((unsigned __int128)1 << 60))
+    return fail(N2V_ERR_INVALID_ARG, "output too large");
+  DevInfo di;
+  int rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  hipError_t e = launch_contexts(d_walks, n_walks, walk_len, window, stride, d_contexts, di, (hipStream_t)hip_stream);
+  return e == hipSuccess ? N2V_OK : hip_fail(e, "contexts launch");
+}
+
+int n2v_negative_samples(n2v_graph g, const int32_t* d_walks, uint64_t n_walks, uint32_t walk_len,
+                         uint32_t n_neg, uint64_t seed, uint64_t walk_id_base, int32_t* d_negatives,
+                         void* hip_stream) {
+  GraphRec* gr = find_graph(g);
+  if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
+  if (walk_len == 0 || n_neg == 0) return fail(N2V_ERR_INVALID_ARG, "walk_len and n_neg must be >= 1");
+  if (n_neg > kMaxNegatives) return fail(N2V_ERR_INVALID_ARG, "n_neg %u above %u", n_neg, kMaxNegatives);
+  if (n_walks > 0 && (!d_walks || !d_negatives)) return fail(N2V_ERR_INVALID_ARG, "walks and negatives must be non-NULL");
+  if ((unsigned __int128)n_walks * walk_len * n_neg >= ((unsigned __int128)1 << 60))
+    return fail(N2V_ERR_INVALID_ARG, "output too large");
+  if (n_walks == 0) return N2V_OK;
+  DevInfo di;
+  int rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  if (di.device != gr->device) return fail(N2V_ERR_INVALID_ARG, "graph lives on device %d, current is %d", gr->device, di.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  int32_t* guide = nullptr;
+  uint32_t shift = 0;
+  if (gr->n_entries > 0) {
+    // The guide table is built once, on this stream, and finished before any
+    // call (on any stream) can use it.
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!gr->neg_guide) {
+      const uint32_t s = neg_guide_shift(gr->dev.n);
+      int32_t* t = nullptr;
+      hipError_t e = hipMalloc(&t, neg_guide_bytes(s, gr->dev.n, gr->dev.m));
+      if (e != hipSuccess) return fail(N2V_ERR_NOMEM, "guide table: %s", hipGetErrorString(e));
+      e = launch_neg_guide(gr->dev, t, s, di, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        hipFree(t);
+        return hip_fail(e, "guide table");
+      }
+      gr->neg_guide = t;
+      gr->neg_shift = s;
+    }
+    guide = gr->neg_guide;
+    shift = gr->neg_shift;
+  }
+  hipError_t e = launch_negatives(gr->dev, guide, shift, d_walks, n_walks, walk_len, n_neg, seed, walk_id_base,
+                                  d_negatives, di, st);
+  return e == hipSuccess ? N2V_OK : hip_fail(e, "negatives launch");
 }
 
 int n2v_set_tuning(const n2v_tuning_t* tuning) {

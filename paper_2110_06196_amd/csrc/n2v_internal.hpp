@@ -91,6 +91,23 @@ hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D,
 hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,
                              uint32_t r_bytes, hipStream_t st);
 
+// Training corpora (n2v_corpus.hip).
+hipError_t launch_contexts(const int32_t* Y, uint64_t n_walks, uint32_t L, uint32_t window, uint32_t stride,
+                           int32_t* C, const DevInfo& di, hipStream_t st);
+constexpr uint32_t kMaxWindow = 1u << 16;     // context window bound (tile words stay in 32 bits)
+constexpr uint32_t kMaxNegatives = 1u << 14;  // negatives per position (one position's staging fits LDS)
+
+// Negative sampling searches through a guide table of 2^shift + 1 int32
+// entries per graph (shift = neg_guide_shift(n), at most kNegGuideMaxShift).
+constexpr uint32_t kNegGuideMaxShift = 28;
+constexpr int kNegGuideShiftAdjust = -1;  // 2^shift: the power of two at or above n, times 2^adjust
+uint32_t neg_guide_shift(int64_t n);
+size_t neg_guide_bytes(uint32_t shift, int64_t n, uint64_t m);
+hipError_t launch_neg_guide(const GraphDev& g, int32_t* guide, uint32_t shift, const DevInfo& di, hipStream_t st);
+hipError_t launch_negatives(const GraphDev& g, const int32_t* guide, uint32_t shift, const int32_t* Y,
+                            uint64_t n_walks, uint32_t L, uint32_t n_neg, uint64_t seed, uint64_t wid_base,
+                            int32_t* N, const DevInfo& di, hipStream_t st);
+
 enum : uint64_t {
   kErrOffsets = 1,   // O[0] != 0, O not monotone or O[n] != m
   kErrOrder = 2,     // a row not strictly increasing

@@ -20,6 +20,8 @@ struct GraphRec {
   uint32_t weighted = 0;
   uint64_t owned_bytes = 0;
   int device = 0;
+  int32_t* neg_guide = nullptr;  // built on the first negative-sampling call
+  uint32_t neg_shift = 0;
 };
 
 extern thread_local std::string t_err;
