@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--negatives", type=int, default=5, help="corpus: negatives per walk position")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (PMC counter calibration)")
+    ap.add_argument("--summarize-corpus-profiles", nargs=5, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
+                                                                      "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="write the corpus kernels' rocprofv3 summaries under profiles/")
     ap.add_argument("--summarize-profiles", nargs=7, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
                                                               "CAL_FETCH_DIR", "CAL_WRITE_DIR", "SQ_DIR",
                                                               "TCC_DIR"),
@@ -90,14 +93,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_chung_lu_1m.txt")
 TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_chung_lu_1m.txt")
 KERNEL_OF_PATH = {"generic": "k_walk_n2v", "fo_weighted": "k_walk_lane", "return_only": "k_walk_lane"}
 COPY_BYTES = 1 << 30
+KERNEL_KEYS = ("k_walk_n2v", "k_walk_lane", "k_walk_queue", "k_contexts_lds", "k_contexts_global", "k_negatives",
+               "k_neg_guide", "copy")
+CORPUS_TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_corpus_chung_lu_1m.txt")
+CORPUS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_corpus_chung_lu_1m.txt")
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary,
+def traffic_from_profiles(kernel: str, path: str = TRAFFIC_FILE):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 PMC summary,
     if it was taken on the current kernel sources (else None)."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m = re.search(r"source_hash:\s*(\w+)", txt)
     if not m or m.group(1) != kernel_source_hash():
         return None
@@ -119,8 +126,7 @@ def _pmc_per_kernel(d, counter):
             if row.get("Counter_Name") != counter:
                 continue
             name = row.get("Kernel_Name", "")
-            key = next((k for k in ("k_walk_n2v", "k_walk_lane", "copy") if k in name.lower() or
-                        (k == "copy" and "copy" in name.lower())), None)
+            key = next((k for k in KERNEL_KEYS if k in name.lower()), None)
             if key is None:
                 key = name[:60]
             vals.setdefault((key, row.get("Dispatch_Id")), 0.0)
@@ -160,16 +166,18 @@ def summarize_counters(sq_dir, tcc_dir, cmds):
     print(open(COUNTER_FILE).read())
 
 
-def summarize_profiles(trace_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cmds):
+def summarize_profiles(trace_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cmds,
+                       trace_file=TRACE_FILE, traffic_file=TRAFFIC_FILE,
+                       title="1M-node Chung-Lu node2vec workload"):
     import csv
-    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-    lines = ["# rocprofv3 --kernel-trace --stats, 1M-node Chung-Lu node2vec workload",
+    os.makedirs(os.path.dirname(traffic_file), exist_ok=True)
+    lines = [f"# rocprofv3 --kernel-trace --stats, {title}",
              f"# command: {cmds['trace']}", "# kernel | calls | total ns | average ns | min ns | max ns"]
     for f in _csvs(trace_dir, "kernel_stats.csv"):
         for row in csv.DictReader(open(f)):
             lines.append(" | ".join([row["Name"][:110], row["Calls"], row["TotalDurationNs"],
                                      row["AverageNs"], row["MinNs"], row["MaxNs"]]))
-    open(TRACE_FILE, "w").write("\n".join(lines) + "\n")
+    open(trace_file, "w").write("\n".join(lines) + "\n")
     fetch = _pmc_per_kernel(fetch_dir, "FETCH_SIZE")
     write = _pmc_per_kernel(write_dir, "WRITE_SIZE")
     cf = _pmc_per_kernel(cal_fetch_dir, "FETCH_SIZE")
@@ -191,9 +199,9 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write
         out.append(f"{k} fetch_bytes_per_launch: {fk:.6e} write_bytes_per_launch: {wk:.6e} "
                    f"dispatches: {fetch.get(k, (0, 0))[1]}")
         out.append(f"{k} hbm_bytes_per_launch: {fk + wk:.6e}")
-    open(TRAFFIC_FILE, "w").write("\n".join(out) + "\n")
-    print(open(TRACE_FILE).read())
-    print(open(TRAFFIC_FILE).read())
+    open(traffic_file, "w").write("\n".join(out) + "\n")
+    print(open(trace_file).read())
+    print(open(traffic_file).read())
 
 
 def copy_calibration():
@@ -266,6 +274,19 @@ def main():
             "sq": f.format(c="SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_INSTS_VALU "
                            "SQ_INSTS_VMEM_RD SQ_INSTS_LDS"),
             "tcc": f.format(c="TCC_HIT_sum TCC_MISS_sum")})
+        return
+    if args.summarize_corpus_profiles:
+        base = "cd /tmp && rocprofv3 {what} --output-format csv -d <dir> -o run -- " \
+               "python3 /root/repo/bench.py --config corpus{extra} --steps {k} --warmup 0 --cpu-seconds 0"
+        c = "cd /tmp && rocprofv3 --pmc {c} --output-format csv -d <dir> -o run -- " \
+            "python3 /root/repo/bench.py --copy-calibration"
+        summarize_profiles(*args.summarize_corpus_profiles, cmds={
+            "trace": base.format(what="--kernel-trace --stats", k=2, extra=""),
+            "fetch": base.format(what="--pmc FETCH_SIZE", k=1, extra=" --walklets ''"),
+            "write": base.format(what="--pmc WRITE_SIZE", k=1, extra=" --walklets ''"),
+            "cal_fetch": c.format(c="FETCH_SIZE"), "cal_write": c.format(c="WRITE_SIZE")},
+            trace_file=CORPUS_TRACE_FILE, traffic_file=CORPUS_TRAFFIC_FILE,
+            title="training corpora of the 1M-node Chung-Lu walks")
         return
     if args.copy_calibration:
         copy_calibration()
@@ -810,7 +831,8 @@ def bench_corpus(args):
     kernels = []
     for i, (name, _, alg) in enumerate(ops):
         ms = float(np.mean([ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)]))
-        kernels.append({"op": name, "mean_ms": ms, "alg_bytes": alg, "alg_GBps": alg / (ms / 1e3) / 1e9,
+        kernels.append({"op": name, "kernel": "k_negatives" if name.startswith("negatives") else "k_contexts_lds",
+                        "mean_ms": ms, "alg_bytes": alg, "alg_GBps": alg / (ms / 1e3) / 1e9,
                         "positions_per_s": npos / (ms / 1e3)})
     dom = max(kernels, key=lambda k: k["mean_ms"])
 
@@ -838,7 +860,8 @@ def bench_corpus(args):
                                   f"{scales}, {n_neg} scale-free negatives per position",
                       "positions": npos},
            "roofline": {"bound": "hbm", "achieved": dom["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": dom["alg_GBps"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom["op"]},
+                        "frac": dom["alg_GBps"] / HBM_PEAK_GBS,
+                        "traffic": traffic_from_profiles(dom["kernel"], CORPUS_TRAFFIC_FILE), "kernel": dom["op"]},
            "cpu_baseline": {"value": rows * L / ct, "unit": "walk positions/s", "cores": 1, "kind": "oracle",
                             "sample": f"walk rows [{r0}, {r0 + rows}) through every corpus op ({ct:.1f} s wall)"},
            "kernels": kernels, "parity_sample": {"rows": rows, "mismatching_rows": mism},
