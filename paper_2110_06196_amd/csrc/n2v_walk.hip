@@ -176,7 +176,8 @@ __device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl,
 // Returns, in lane l < nk, whether its key is in A and (if so) its index.
 
 // One whole walk (row w of request a) by one group of G lanes; mem is the
-// group's LDS region of group_lds_words(tile, cap, G) words.
+// group's LDS region of group_lds_words(tile, cap, G) words.  FULL adds the
+// approximated step and the forced two-pass route to the exact routes.
 // Splitters of a long sorted row A[0..n) (n >= 4G): the group loads A[l n / G]
 // for its G lanes into LDS (one coalesced round), and every lane can then
 // bisect a key among the splitters in LDS and the key's 1/G slice of A in
@@ -206,7 +207,7 @@ __device__ __forceinline__ uint32_t lower_bound_split(const int32_t* __restrict_
   return b + lower_bound_i32(A + b, e - b, y);
 }
 
-template <int G, bool WEIGHTED, typename RT>
+template <int G, bool WEIGHTED, typename RT, bool FULL>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
                                            int mode_knob) {
   const int lane = threadIdx.x & 63;
@@ -379,8 +380,8 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           }
         };
 
-        if (a.k_approx != 0 && d > a.k_approx) {
-          approx_step();
+        if (FULL && a.k_approx != 0 && d > a.k_approx) {
+          if constexpr (FULL) approx_step();
         } else if (!a.second_order || t < 0) {
           // First-order step (also the first step of a node2vec walk).
           if (S == 0) break;
@@ -410,8 +411,8 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
                                   : (stream <= merge ? kModeStream : kModeMerge);
           }
-          if (mode == kModeTwoPass) {
-            two_pass();
+          if (FULL && mode == kModeTwoPass) {
+            if constexpr (FULL) two_pass();
           } else {
             // List the positions j in N(v) whose candidate is a common
             // neighbour (x in N(t), x != t), in increasing j, one LDS page of
@@ -651,7 +652,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   }
 }
 
-template <int G, bool WEIGHTED, typename RT>
+template <int G, bool WEIGHTED, typename RT, bool FULL>
 __global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 7 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
   extern __shared__ int32_t lds[];
   const int gib = threadIdx.x / G;
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 7 :
   int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap, G);
   const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
   for (uint64_t w = (uint64_t)blockIdx.x * gpb + gib; w < a.nwalks; w += ngroups)
-    group_walk<G, WEIGHTED, RT>(a, w, mem, tile, cap, mode_knob);
+    group_walk<G, WEIGHTED, RT, FULL>(a, w, mem, tile, cap, mode_knob);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,11 +702,11 @@ __global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkA
     if (a.path != (uint32_t)Path::kGeneric) {
       for (uint64_t w = ch.w0 + (uint64_t)gl; w < ch.w1; w += G) lane_dispatch<G>(a, w);
     } else if (a.g.W == nullptr) {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, false, uint32_t>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, false, uint32_t, true>(a, w, mem, tile, cap, mode_knob);
     } else if (a.g.r_bytes == 8) {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint64_t>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint64_t, true>(a, w, mem, tile, cap, mode_knob);
     } else {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint32_t>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint32_t, true>(a, w, mem, tile, cap, mode_knob);
     }
   }
 }
@@ -747,7 +748,8 @@ hipError_t go_lane(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, h
 
 template <int G, bool WEIGHTED, typename RT>
 hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
-  auto k = k_walk_n2v<G, WEIGHTED, RT>;
+  const bool full = a.k_approx != 0 || cfg.mode == kModeTwoPass;
+  auto k = full ? k_walk_n2v<G, WEIGHTED, RT, true> : k_walk_n2v<G, WEIGHTED, RT, false>;
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
