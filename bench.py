@@ -81,11 +81,15 @@ def graph_cache():
     return O, D, W
 
 
-def kernel_source_hash() -> str:
+WALK_SOURCES = ("n2v_walk.hip", "n2v_device.hpp", "n2v_internal.hpp")
+CORPUS_SOURCES = ("n2v_corpus.hip", "n2v_device.hpp", "n2v_internal.hpp")
+
+
+def kernel_source_hash(files=WALK_SOURCES) -> str:
+    """Hash of the device sources the profiled kernels are built from."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2110_06196_amd", "csrc"))):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(ROOT, "paper_2110_06196_amd", "csrc", f), "rb").read())
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2110_06196_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -99,14 +103,14 @@ CORPUS_TRACE_FILE = os.path.join(ROOT, "profiles", "kernel_trace_corpus_chung_lu
 CORPUS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_corpus_chung_lu_1m.txt")
 
 
-def traffic_from_profiles(kernel: str, path: str = TRAFFIC_FILE):
+def traffic_from_profiles(kernel: str, path: str = TRAFFIC_FILE, files=WALK_SOURCES):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 PMC summary,
     if it was taken on the current kernel sources (else None)."""
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m = re.search(r"source_hash:\s*(\w+)", txt)
-    if not m or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash(files):
         return None
     m = re.search(rf"^{re.escape(kernel)}\s+hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
     return float(m.group(1)) if m else None
@@ -168,7 +172,7 @@ def summarize_counters(sq_dir, tcc_dir, cmds):
 
 def summarize_profiles(trace_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, cmds,
                        trace_file=TRACE_FILE, traffic_file=TRAFFIC_FILE,
-                       title="1M-node Chung-Lu node2vec workload"):
+                       title="1M-node Chung-Lu node2vec workload", files=WALK_SOURCES):
     import csv
     os.makedirs(os.path.dirname(traffic_file), exist_ok=True)
     lines = [f"# rocprofv3 --kernel-trace --stats, {title}",
@@ -190,7 +194,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, cal_fetch_dir, cal_write
            "# per dispatch), each scaled by what the same counter reads for a plain 1 GiB copy.",
            f"# fetch command: {cmds['fetch']}", f"# write command: {cmds['write']}",
            f"# calibration commands: {cmds['cal_fetch']} ; {cmds['cal_write']}",
-           f"source_hash: {kernel_source_hash()}",
+           f"source_hash: {kernel_source_hash(files)}",
            f"copy_fetch_KiB: {cal_f}", f"copy_write_KiB: {cal_w}",
            f"fetch_scale: {f_scale:.6f}", f"write_scale: {w_scale:.6f}"]
     for k in sorted(set(fetch) | set(write)):
@@ -286,7 +290,7 @@ def main():
             "write": base.format(what="--pmc WRITE_SIZE", k=1, extra=" --walklets ''"),
             "cal_fetch": c.format(c="FETCH_SIZE"), "cal_write": c.format(c="WRITE_SIZE")},
             trace_file=CORPUS_TRACE_FILE, traffic_file=CORPUS_TRAFFIC_FILE,
-            title="training corpora of the 1M-node Chung-Lu walks")
+            title="training corpora of the 1M-node Chung-Lu walks", files=CORPUS_SOURCES)
         return
     if args.copy_calibration:
         copy_calibration()
@@ -861,11 +865,12 @@ def bench_corpus(args):
                       "positions": npos},
            "roofline": {"bound": "hbm", "achieved": dom["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": dom["alg_GBps"] / HBM_PEAK_GBS,
-                        "traffic": traffic_from_profiles(dom["kernel"], CORPUS_TRAFFIC_FILE), "kernel": dom["op"]},
+                        "traffic": traffic_from_profiles(dom["kernel"], CORPUS_TRAFFIC_FILE, CORPUS_SOURCES),
+                        "kernel": dom["op"]},
            "cpu_baseline": {"value": rows * L / ct, "unit": "walk positions/s", "cores": 1, "kind": "oracle",
                             "sample": f"walk rows [{r0}, {r0 + rows}) through every corpus op ({ct:.1f} s wall)"},
            "kernels": kernels, "parity_sample": {"rows": rows, "mismatching_rows": mism},
-           "kernel_source_hash": kernel_source_hash()}
+           "kernel_source_hash": kernel_source_hash(CORPUS_SOURCES)}
     print(json.dumps(out), flush=True)
     n2v.n2v_graph_release(g)
 
