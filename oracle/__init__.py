@@ -91,8 +91,31 @@ def lib():
             L.n2vo_negatives.argtypes = [u64p, ctypes.c_int64, i32p, ctypes.c_int64, ctypes.c_uint32,
                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, i32p]
             L.n2vo_negatives.restype = None
+            shp = ctypes.POINTER(EFShape)
+            L.n2vo_ef_shape_of.argtypes = [ctypes.c_uint64, ctypes.c_uint64, shp]
+            L.n2vo_ef_shape_of.restype = None
+            L.n2vo_ef_graph_shape.argtypes = [ctypes.c_int64, ctypes.c_uint64, shp]
+            L.n2vo_ef_graph_shape.restype = ctypes.c_int
+            L.n2vo_ef_words.argtypes = [shp, ctypes.c_uint32, u64p, u64p, u64p, u64p]
+            L.n2vo_ef_words.restype = None
+            L.n2vo_ef_encode.argtypes = [u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, u64p, u64p, u64p,
+                                         u64p]
+            L.n2vo_ef_encode.restype = ctypes.c_int
+            L.n2vo_ef_encode_graph.argtypes = [u64p, ctypes.c_int64, i32p, ctypes.c_uint64, ctypes.c_uint32, u64p,
+                                               u64p, u64p, u64p]
+            L.n2vo_ef_encode_graph.restype = ctypes.c_int
+            L.n2vo_ef_select.argtypes = [shp, u64p, u64p, ctypes.c_uint64]
+            L.n2vo_ef_select.restype = ctypes.c_uint64
+            L.n2vo_ef_rank.argtypes = [shp, u64p, u64p, ctypes.c_uint64]
+            L.n2vo_ef_rank.restype = ctypes.c_uint64
             _lib = L
     return _lib
+
+
+class EFShape(ctypes.Structure):
+    """n2vo_ef_shape: k, l, u, m, n_zeros, h_bits."""
+    _fields_ = [("k", ctypes.c_uint32), ("l", ctypes.c_uint32), ("u", ctypes.c_uint64), ("m", ctypes.c_uint64),
+                ("n_zeros", ctypes.c_uint64), ("h_bits", ctypes.c_uint64)]
 
 
 class OracleError(RuntimeError):
@@ -250,3 +273,60 @@ def negatives(offsets, Y, n_neg: int, seed: int, walk_id_base: int = 0):
     lib().n2vo_negatives(_p(O, ctypes.c_uint64), O.size - 1, _p(Yc, ctypes.c_int32), nw, L, n_neg, seed,
                          walk_id_base, _p(N, ctypes.c_int32))
     return N
+
+
+def _ef_arrays(shape, q):
+    u64 = ctypes.c_uint64
+    hw, lw, n1, n0 = u64(), u64(), u64(), u64()
+    lib().n2vo_ef_words(ctypes.byref(shape), q, ctypes.byref(hw), ctypes.byref(lw), ctypes.byref(n1),
+                        ctypes.byref(n0))
+    mk = lambda k: np.zeros(max(1, k.value), dtype=np.uint64)
+    return mk(hw), mk(lw), mk(n1), mk(n0)
+
+
+def ef_encode(values, u: int, q: int = 1024) -> dict:
+    """Elias-Fano list of non-decreasing values below u (see n2v_oracle.h):
+    dict with the shape fields and the arrays H, L, S1, S0 (uint64)."""
+    y = np.ascontiguousarray(values, dtype=np.uint64)
+    shape = EFShape()
+    lib().n2vo_ef_shape_of(y.size, u, ctypes.byref(shape))
+    H, L, S1, S0 = _ef_arrays(shape, q)
+    rc = lib().n2vo_ef_encode(_p(y, ctypes.c_uint64), y.size, u, q, _p(H, ctypes.c_uint64),
+                              _p(L, ctypes.c_uint64), _p(S1, ctypes.c_uint64), _p(S0, ctypes.c_uint64))
+    if rc != OK:
+        raise OracleError(rc)
+    return _ef_dict(shape, q, H, L, S1, S0)
+
+
+def ef_encode_graph(offsets, dst, q: int = 1024) -> dict:
+    """Elias-Fano list of the edge codes phi_k(a, b) = a 2^k + b of a sorted CSR graph."""
+    O = np.ascontiguousarray(offsets, dtype=np.uint64)
+    D = np.ascontiguousarray(dst, dtype=np.int32)
+    n = O.size - 1
+    shape = EFShape()
+    if lib().n2vo_ef_graph_shape(n, D.size, ctypes.byref(shape)) != OK:
+        raise OracleError(ERR_INVALID_ARG)
+    H, L, S1, S0 = _ef_arrays(shape, q)
+    rc = lib().n2vo_ef_encode_graph(_p(O, ctypes.c_uint64), n, _p(D, ctypes.c_int32), D.size, q,
+                                    _p(H, ctypes.c_uint64), _p(L, ctypes.c_uint64), _p(S1, ctypes.c_uint64),
+                                    _p(S0, ctypes.c_uint64))
+    if rc != OK:
+        raise OracleError(rc)
+    return _ef_dict(shape, q, H, L, S1, S0)
+
+
+def _ef_dict(shape, q, H, L, S1, S0):
+    return {"k": shape.k, "l": shape.l, "u": shape.u, "m": shape.m, "n_zeros": shape.n_zeros,
+            "h_bits": shape.h_bits, "q": q, "H": H, "L": L, "S1": S1, "S0": S0, "_shape": shape}
+
+
+def ef_select(ef: dict, i: int) -> int:
+    """The i-th smallest element (plain scan of H)."""
+    return int(lib().n2vo_ef_select(ctypes.byref(ef["_shape"]), _p(ef["H"], ctypes.c_uint64),
+                                    _p(ef["L"], ctypes.c_uint64), i))
+
+
+def ef_rank(ef: dict, x: int) -> int:
+    """The number of elements strictly below x (plain scan of H)."""
+    return int(lib().n2vo_ef_rank(ctypes.byref(ef["_shape"]), _p(ef["H"], ctypes.c_uint64),
+                                  _p(ef["L"], ctypes.c_uint64), x))

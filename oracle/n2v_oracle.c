@@ -333,3 +333,120 @@ void n2vo_negatives(const uint64_t* O, int64_t n, const int32_t* Y, int64_t nw, 
     }
   }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Elias-Fano list and the edge-code list of a graph (Methods, "Memory       */
+/* Complexity", "Edge Encoding", "Efficient implementation of Elias-Fano"). */
+/* ------------------------------------------------------------------------ */
+void n2vo_ef_shape_of(uint64_t m, uint64_t u, n2vo_ef_shape* s) {
+  s->k = 0;
+  s->u = u;
+  s->m = m;
+  /* l = floor(log2(u / m)): the largest l with m 2^l <= u */
+  uint32_t l = 0;
+  if (m > 0) {
+    uint64_t ratio = u / m; /* floor(log2(u/m)) == floor(log2(floor(u/m))) */
+    while (l < 63 && (ratio >> (l + 1)) > 0) ++l;
+  }
+  s->l = l;
+  s->n_zeros = ((u - 1) >> l) + 1;
+  s->h_bits = m + s->n_zeros;
+}
+
+void n2vo_ef_words(const n2vo_ef_shape* s, uint32_t q, uint64_t* h_words, uint64_t* l_words,
+                   uint64_t* s1_len, uint64_t* s0_len) {
+  *h_words = (s->h_bits + 63) / 64;
+  *l_words = (s->m * s->l + 63) / 64;
+  *s1_len = (s->m + q - 1) / q;
+  *s0_len = (s->n_zeros + q - 1) / q;
+}
+
+static int get_bit(const uint64_t* H, uint64_t p) { return (int)((H[p / 64] >> (p % 64)) & 1u); }
+
+static uint64_t get_low(const uint64_t* L, uint32_t l, uint64_t i) {
+  uint64_t v = 0;
+  for (uint32_t b = 0; b < l; ++b) { /* bit by bit: plain */
+    uint64_t p = i * l + b;
+    v |= ((L[p / 64] >> (p % 64)) & 1u) << b;
+  }
+  return v;
+}
+
+int n2vo_ef_encode(const uint64_t* y, uint64_t m, uint64_t u, uint32_t q, uint64_t* H, uint64_t* L,
+                   uint64_t* S1, uint64_t* S0) {
+  if (u == 0 || q == 0) return N2VO_ERR_INVALID_ARG;
+  for (uint64_t i = 0; i < m; ++i)
+    if (y[i] >= u || (i > 0 && y[i] < y[i - 1])) return N2VO_ERR_INVALID_ARG;
+  n2vo_ef_shape s;
+  n2vo_ef_shape_of(m, u, &s);
+  uint64_t hw, lw, n1, n0;
+  n2vo_ef_words(&s, q, &hw, &lw, &n1, &n0);
+  for (uint64_t w = 0; w < hw; ++w) H[w] = 0;
+  for (uint64_t w = 0; w < lw; ++w) L[w] = 0;
+  for (uint64_t i = 0; i < m; ++i) {
+    uint64_t h = y[i] >> s.l;
+    uint64_t p = h + i; /* h zeros and i ones precede this one */
+    H[p / 64] |= 1ull << (p % 64);
+    for (uint32_t b = 0; b < s.l; ++b) {
+      uint64_t bit = (y[i] >> b) & 1u;
+      uint64_t pl = i * s.l + b;
+      L[pl / 64] |= bit << (pl % 64);
+    }
+  }
+  /* the quantum indexes: one linear pass over H */
+  uint64_t ones = 0, zeros = 0;
+  for (uint64_t p = 0; p < s.h_bits; ++p) {
+    if (get_bit(H, p)) {
+      if (ones % q == 0) S1[ones / q] = p;
+      ++ones;
+    } else {
+      if (zeros % q == 0) S0[zeros / q] = p;
+      ++zeros;
+    }
+  }
+  return (ones == m && zeros == s.n_zeros) ? N2VO_OK : N2VO_ERR_INVALID_ARG;
+}
+
+int n2vo_ef_graph_shape(int64_t n, uint64_t m, n2vo_ef_shape* s) {
+  if (n < 1) return N2VO_ERR_INVALID_ARG;
+  uint32_t k = 0;
+  while ((1ll << k) < n) ++k; /* k = ceil(log2 n) */
+  n2vo_ef_shape_of(m, (uint64_t)n << k, s);
+  s->k = k;
+  return N2VO_OK;
+}
+
+int n2vo_ef_encode_graph(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m, uint32_t q, uint64_t* H,
+                         uint64_t* L, uint64_t* S1, uint64_t* S0) {
+  n2vo_ef_shape s;
+  if (n2vo_ef_graph_shape(n, m, &s) != N2VO_OK) return N2VO_ERR_INVALID_ARG;
+  if (n2vo_validate(O, n, D, m) != N2VO_OK) return N2VO_ERR_INVALID_ARG;
+  uint64_t* y = (uint64_t*)malloc((m ? m : 1) * sizeof(uint64_t));
+  if (!y) return N2VO_ERR_INVALID_ARG;
+  for (int64_t a = 0; a < n; ++a)
+    for (uint64_t i = O[a]; i < O[a + 1]; ++i) y[i] = ((uint64_t)a << s.k) | (uint64_t)D[i]; /* phi_k(a, b) */
+  int rc = n2vo_ef_encode(y, m, s.u, q, H, L, S1, S0);
+  free(y);
+  return rc;
+}
+
+uint64_t n2vo_ef_select(const n2vo_ef_shape* s, const uint64_t* H, const uint64_t* L, uint64_t i) {
+  uint64_t ones = 0;
+  for (uint64_t p = 0; p < s->h_bits; ++p) {
+    if (!get_bit(H, p)) continue;
+    if (ones == i) return ((p - i) << s->l) | get_low(L, s->l, i);
+    ++ones;
+  }
+  return ~0ull; /* i >= m */
+}
+
+uint64_t n2vo_ef_rank(const n2vo_ef_shape* s, const uint64_t* H, const uint64_t* L, uint64_t x) {
+  uint64_t ones = 0;
+  for (uint64_t p = 0; p < s->h_bits; ++p) {
+    if (!get_bit(H, p)) continue;
+    uint64_t y = ((p - ones) << s->l) | get_low(L, s->l, ones);
+    if (y >= x) return ones; /* the list is non-decreasing */
+    ++ones;
+  }
+  return ones;
+}

@@ -123,6 +123,51 @@ void n2vo_contexts(const int32_t* Y, int64_t nw, uint32_t L, uint32_t window, ui
 void n2vo_negatives(const uint64_t* O, int64_t n, const int32_t* Y, int64_t nw, uint32_t L, uint32_t n_neg,
                     uint64_t seed, uint64_t walk_id_base, int32_t* N);
 
+/* ------------------------------------------------------------------------
+ * Elias-Fano (Methods, "Memory Complexity", "Edge Encoding", "Operations on
+ * Elias-Fano", "Efficient implementation of Elias-Fano").
+ *
+ * A non-decreasing list of m integers below u is stored with
+ * l = floor(log2(u / m)) low bits each (l = 0 when m == 0 or u < 2m): the
+ * low parts go to L, field i occupying bits [i l, (i + 1) l) of a stream of
+ * 64-bit words, least significant bit first; the high parts h_i = y_i >> l go
+ * to the bit vector H as the inverted unary codes of their gaps, so the one of
+ * element i is bit h_i + i (bit p = bit p mod 64 of word p / 64), and H holds
+ * n_zeros = ((u - 1) >> l) + 1 zeros, m + n_zeros bits in all.  The quantum
+ * indexes hold S1[j] = position of one number j q and S0[j] = position of
+ * zero number j q (numbers from 0).
+ *
+ * A graph on n nodes is the list of its edge codes phi_k(a, b) = a 2^k + b,
+ * k = ceil(log2 n), in CSR order, with u = n 2^k.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint32_t k;        /* bits of a node id in an edge code (graphs only) */
+  uint32_t l;        /* low bits per element */
+  uint64_t u;        /* every element is below u */
+  uint64_t m;        /* elements */
+  uint64_t n_zeros;  /* zeros of H */
+  uint64_t h_bits;   /* m + n_zeros */
+} n2vo_ef_shape;
+
+/* Shape of an Elias-Fano list of m elements below u (u >= 1). */
+void n2vo_ef_shape_of(uint64_t m, uint64_t u, n2vo_ef_shape* s);
+/* Word counts of H, L, S1 and S0 for a shape and quantum q. */
+void n2vo_ef_words(const n2vo_ef_shape* s, uint32_t q, uint64_t* h_words, uint64_t* l_words,
+                   uint64_t* s1_len, uint64_t* s0_len);
+/* Encode a non-decreasing list y[0..m) below u; the output arrays (sizes from
+ * n2vo_ef_words) are overwritten.  Returns N2VO_OK or N2VO_ERR_INVALID_ARG. */
+int n2vo_ef_encode(const uint64_t* y, uint64_t m, uint64_t u, uint32_t q, uint64_t* H, uint64_t* L,
+                   uint64_t* S1, uint64_t* S0);
+/* The edge list of a sorted CSR graph on n >= 1 nodes: shape (with k) and
+ * encoding as above.  Returns N2VO_OK or N2VO_ERR_INVALID_ARG. */
+int n2vo_ef_graph_shape(int64_t n, uint64_t m, n2vo_ef_shape* s);
+int n2vo_ef_encode_graph(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m, uint32_t q, uint64_t* H,
+                         uint64_t* L, uint64_t* S1, uint64_t* S0);
+/* select(i): the i-th smallest element (i < m), by scanning H from bit 0. */
+uint64_t n2vo_ef_select(const n2vo_ef_shape* s, const uint64_t* H, const uint64_t* L, uint64_t i);
+/* rank(x): the number of elements strictly below x, by scanning H from bit 0. */
+uint64_t n2vo_ef_rank(const n2vo_ef_shape* s, const uint64_t* H, const uint64_t* L, uint64_t x);
+
 /* All reps*ns walks, row w = rep*ns + i. */
 int n2vo_walks(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
                const uint32_t* W, const int32_t* S, int64_t ns,
