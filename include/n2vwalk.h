@@ -75,7 +75,11 @@ typedef struct {
   uint32_t weighted;       /* 1 if weights were given */
   uint32_t prefix_bytes;   /* 0 (unweighted), 4 or 8: width of the per-row weight prefix */
   uint64_t device_bytes;   /* library-owned device memory held by this graph */
+  uint32_t storage;        /* N2V_STORAGE_CSR or N2V_STORAGE_EF */
+  uint32_t ef_quantum;     /* quantum of the Elias-Fano indexes (0 for CSR) */
 } n2v_graph_info_t;
+
+enum { N2V_STORAGE_CSR = 0, N2V_STORAGE_EF = 1 };
 
 /* Launch tuning.  Zero fields mean "automatic".  Tuning never changes a walk:
  * every setting produces bit-identical output. */
@@ -121,6 +125,47 @@ int n2v_graph_info(n2v_graph g, n2v_graph_info_t* out);
 /* Frees the library-owned arrays.  The caller must make sure no walk on g is
  * still running (synchronise the streams first). */
 int n2v_graph_release(n2v_graph g);
+
+/* ---------------------------------------------------------------------------
+ * Elias-Fano graph store (Methods, "Edge Encoding", "Operations on
+ * Elias-Fano", "Efficient implementation of Elias-Fano").
+ *
+ * n2v_graph_upload_ef takes the same CSR arrays as n2v_graph_upload, builds on
+ * the device the Elias-Fano list of the edge codes phi_k(a, b) = a 2^k + b
+ * (k = ceil(log2 n_nodes), u = n_nodes 2^k): l = floor(log2(u / n_entries))
+ * low bits per code in L (field i = bits [i l, (i + 1) l) of little-endian
+ * 64-bit words), the high parts as inverted unary gaps in the bit vector H
+ * (the one of code i is bit (code_i >> l) + i; ((u - 1) >> l) + 1 zeros), and
+ * quantum indexes S1[j] / S0[j] = position of one / zero number j * quantum.
+ * quantum: a power of two in [8, 65536], 0 for 256.  For weighted graphs the
+ * per-row weight prefix is kept (weights are its differences).  The handle
+ * owns everything: the CSR arrays are not referenced after the call returns
+ * (synchronous), so the caller may free them.
+ * Walks (n2v_walks_first_order, n2v_walks_node2vec) and negatives on such a
+ * handle are the same as on the CSR handle of the same graph, bit for bit;
+ * approximated walks, batches and servers need a CSR handle (INVALID_ARG).
+ * Errors: as n2v_graph_upload; INVALID_ARG for n_nodes == 0 or a bad quantum.
+ * ------------------------------------------------------------------------- */
+int n2v_graph_upload_ef(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst,
+                        uint64_t n_entries, const uint32_t* d_weights, uint32_t quantum,
+                        void* hip_stream, n2v_graph* out);
+
+typedef struct {
+  uint32_t k, l, quantum, pad;
+  uint64_t u, n_codes, n_zeros, h_bits;
+  uint64_t h_words, l_words, s1_len, s0_len; /* lengths in uint64 of H, L, S1, S0 */
+  const uint64_t* d_H;                       /* device arrays, owned by the graph */
+  const uint64_t* d_L;
+  const uint64_t* d_S1;
+  const uint64_t* d_S0;
+} n2v_ef_info_t;
+/* INVALID_ARG unless g is an Elias-Fano handle. */
+int n2v_ef_info(n2v_graph g, n2v_ef_info_t* out);
+/* d_out[i] = select(d_idx[i]) (the code of rank d_idx[i]; UINT64_MAX when
+ * d_idx[i] >= n_codes) and rank(d_x[i]) (codes strictly below d_x[i]); device
+ * uint64 arrays of length count, enqueued on hip_stream. */
+int n2v_ef_select(n2v_graph g, const uint64_t* d_idx, uint64_t count, uint64_t* d_out, void* hip_stream);
+int n2v_ef_rank(n2v_graph g, const uint64_t* d_x, uint64_t count, uint64_t* d_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Plain walk generation (one launch per call).

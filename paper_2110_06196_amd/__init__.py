@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libn2vwalk.so")
 N2V_OK, N2V_PENDING = 0, 1
 N2V_ERR_INVALID_ARG, N2V_ERR_UNSORTED, N2V_ERR_OVERFLOW = -1, -2, -3
 N2V_ERR_NOMEM, N2V_ERR_HIP, N2V_ERR_BAD_HANDLE, N2V_ERR_REJECTED = -4, -5, -6, -7
+N2V_STORAGE_CSR, N2V_STORAGE_EF = 0, 1
 N2V_FIRST_ORDER, N2V_NODE2VEC = 0, 1
 N2V_TUNE_GENERIC_ONLY = 1
 N2V_ROUTE_AUTO, N2V_ROUTE_TWO_PASS, N2V_ROUTE_PROBE, N2V_ROUTE_STREAM, N2V_ROUTE_MERGE = 0, 1, 2, 3, 4
@@ -42,7 +43,17 @@ class GraphInfo(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_uint64), ("n_entries", ctypes.c_uint64),
                 ("max_degree", ctypes.c_uint64), ("max_row_wsum", ctypes.c_uint64),
                 ("sum_deg_sq", ctypes.c_uint64), ("weighted", ctypes.c_uint32),
-                ("prefix_bytes", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
+                ("prefix_bytes", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
+                ("storage", ctypes.c_uint32), ("ef_quantum", ctypes.c_uint32)]
+
+
+class EFInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("l", ctypes.c_uint32), ("quantum", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("u", ctypes.c_uint64), ("n_codes", ctypes.c_uint64),
+                ("n_zeros", ctypes.c_uint64), ("h_bits", ctypes.c_uint64), ("h_words", ctypes.c_uint64),
+                ("l_words", ctypes.c_uint64), ("s1_len", ctypes.c_uint64), ("s0_len", ctypes.c_uint64),
+                ("d_H", ctypes.c_void_p), ("d_L", ctypes.c_void_p), ("d_S1", ctypes.c_void_p),
+                ("d_S0", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -82,6 +93,10 @@ SIGNATURES = {
     "n2v_walks_first_order": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP, _VP],
     "n2v_walks_node2vec": [_U64, _VP, _U64, _U32, _U32, _D, _D, _U64, _U64, _VP, _VP, _VP],
     "n2v_walks_approximated": [_U64, _U32, _VP, _U64, _U32, _U32, _D, _D, _U32, _U64, _U64, _VP, _VP, _VP],
+    "n2v_graph_upload_ef": [_VP, _U64, _VP, _U64, _VP, _U32, _VP, ctypes.POINTER(ctypes.c_uint64)],
+    "n2v_ef_info": [_U64, ctypes.POINTER(EFInfo)],
+    "n2v_ef_select": [_U64, _VP, _U64, _VP, _VP],
+    "n2v_ef_rank": [_U64, _VP, _U64, _VP, _VP],
     "n2v_walk_contexts": [_VP, _U64, _U32, _U32, _U32, _VP, _VP],
     "n2v_negative_samples": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP],
     "n2v_set_tuning": [ctypes.POINTER(Tuning)],
@@ -170,6 +185,58 @@ def n2v_graph_info(g: int) -> dict:
     info = GraphInfo()
     _check(lib().n2v_graph_info(g, ctypes.byref(info)))
     return {k: getattr(info, k) for k, _ in GraphInfo._fields_}
+
+
+def n2v_graph_upload_ef(offsets, dst, weights=None, quantum: int = 0, stream=None) -> int:
+    """Build an Elias-Fano graph from CSR device tensors (same layout as
+    n2v_graph_upload).  The tensors are not referenced after the call."""
+    if offsets.dtype == torch.int64:
+        offsets = offsets.view(torch.uint64) if hasattr(torch, "uint64") else offsets
+    _dev(dst, torch.int32, "dst")
+    if weights is not None and weights.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        raise N2VError(N2V_ERR_INVALID_ARG, "weights must be uint32 (or int32 bit pattern)")
+    h = ctypes.c_uint64(0)
+    _check(lib().n2v_graph_upload_ef(_ptr(offsets), offsets.numel() - 1, _ptr(dst), dst.numel(), _ptr(weights),
+                                     quantum, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def n2v_ef_info(g: int) -> dict:
+    """Shape of an Elias-Fano graph and the device addresses of its arrays (d_H, d_L, d_S1, d_S0)."""
+    info = EFInfo()
+    _check(lib().n2v_ef_info(g, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in EFInfo._fields_ if f != "pad"}
+
+
+def ef_arrays(g: int) -> dict:
+    """Copies of the Elias-Fano arrays H, L, S1, S0 of graph g as device int64 tensors."""
+    info = n2v_ef_info(g)
+    out = {}
+    for name, n in (("H", info["h_words"]), ("L", info["l_words"]), ("S1", info["s1_len"]), ("S0", info["s0_len"])):
+        t = torch.empty(max(int(n), 1), dtype=torch.int64, device="cuda")
+        if n:
+            torch.cuda.synchronize()
+            rc = _hip().hipMemcpy(t.data_ptr(), info["d_" + name], int(n) * 8, 3)  # device to device
+            if rc != 0:
+                raise N2VError(N2V_ERR_HIP, f"hipMemcpy failed ({rc})")
+        out[name] = t[:int(n)]
+    return out
+
+
+def n2v_ef_select(g: int, idx, out=None, stream=None):
+    _dev(idx, torch.int64, "idx")
+    if out is None:
+        out = torch.empty_like(idx)
+    _check(lib().n2v_ef_select(g, _ptr(idx), idx.numel(), _ptr(out), _stream(stream)))
+    return out
+
+
+def n2v_ef_rank(g: int, x, out=None, stream=None):
+    _dev(x, torch.int64, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().n2v_ef_rank(g, _ptr(x), x.numel(), _ptr(out), _stream(stream)))
+    return out
 
 
 def n2v_graph_release(g: int) -> None:

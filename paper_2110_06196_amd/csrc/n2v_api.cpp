@@ -192,27 +192,31 @@ extern "C" {
 
 const char* n2v_last_error(void) { return t_err.c_str(); }
 
-int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst,
-                     uint64_t n_entries, const uint32_t* d_weights, uint32_t flags,
-                     void* hip_stream, n2v_graph* out) {
-  if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
-  *out = 0;
+}  // extern "C"
+
+namespace n2v {
+namespace {
+
+// Validate a CSR on the device and collect its statistics: h = {error bits,
+// max degree, max row weight sum, sum of squared degrees}.
+// Host-side argument checks of a CSR upload (before any device call).
+int check_csr_args(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst, uint64_t n_entries) {
   if (!d_offsets) return fail(N2V_ERR_INVALID_ARG, "offsets is NULL");
   if (n_entries > 0 && !d_dst) return fail(N2V_ERR_INVALID_ARG, "dst is NULL");
-  if (flags != 0) return fail(N2V_ERR_INVALID_ARG, "flags must be 0");
   if (n_nodes > (uint64_t)INT32_MAX) return fail(N2V_ERR_INVALID_ARG, "node ids must fit in int32");
   if (n_entries >= ((uint64_t)1 << 62)) return fail(N2V_ERR_INVALID_ARG, "too many entries");
-  DevInfo di;
-  int rc = current_devinfo(&di);
-  if (rc != N2V_OK) return rc;
-  hipStream_t st = (hipStream_t)hip_stream;
+  return N2V_OK;
+}
+
+int validate_csr(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst, uint64_t n_entries,
+                 const uint32_t* d_weights, hipStream_t st, uint64_t h[4]) {
   uint64_t* d_stats = nullptr;
   hipError_t e = hipMalloc(&d_stats, 4 * sizeof(uint64_t));
   if (e != hipSuccess) return fail(N2V_ERR_NOMEM, "hipMalloc stats: %s", hipGetErrorString(e));
-  uint64_t h[4] = {0, 0, 0, 0};
+  h[0] = h[1] = h[2] = h[3] = 0;
   e = hipMemsetAsync(d_stats, 0, 4 * sizeof(uint64_t), st);
   if (e == hipSuccess) e = launch_validate_stats(d_offsets, (int64_t)n_nodes, d_dst, n_entries, d_weights, d_stats, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(h, d_stats, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d_stats, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   hipFree(d_stats);
   if (e != hipSuccess) return hip_fail(e, "graph validation");
@@ -221,10 +225,11 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
                 (h[0] & kErrOrder) ? " row-not-strictly-increasing" : "",
                 (h[0] & kErrRange) ? " destination-out-of-range" : "");
   }
+  return N2V_OK;
+}
+
+GraphRec* new_record(uint64_t n_nodes, uint64_t n_entries, const uint64_t h[4], bool weighted, int device) {
   GraphRec* gr = new GraphRec();
-  gr->dev.O = d_offsets;
-  gr->dev.D = d_dst;
-  gr->dev.W = d_weights;
   gr->dev.n = (int64_t)n_nodes;
   gr->dev.m = n_entries;
   gr->n_nodes = n_nodes;
@@ -232,35 +237,182 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
   gr->max_degree = h[1];
   gr->max_row_wsum = h[2];
   gr->sum_deg_sq = h[3];
-  gr->weighted = d_weights ? 1u : 0u;
-  gr->device = di.device;
-  if (d_weights && n_entries > 0) {
-    const uint32_t rb = gr->max_row_wsum <= 0xFFFFFFFFull ? 4u : 8u;
-    void* R = nullptr;
-    e = hipMalloc(&R, (size_t)n_entries * rb);
-    if (e != hipSuccess) {
-      delete gr;
-      return fail(N2V_ERR_NOMEM, "hipMalloc prefix (%llu bytes): %s",
-                  (unsigned long long)(n_entries * rb), hipGetErrorString(e));
-    }
-    e = launch_row_prefix(d_offsets, (int64_t)n_nodes, d_weights, R, rb, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-      hipFree(R);
-      delete gr;
-      return hip_fail(e, "row prefix");
-    }
-    gr->dev.R = R;
-    gr->dev.r_bytes = rb;
-    gr->owned_bytes += (uint64_t)n_entries * rb;
+  gr->weighted = weighted ? 1u : 0u;
+  gr->device = device;
+  return gr;
+}
+
+// The per-row inclusive weight prefix (owned), 32-bit when every row sum fits.
+int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weights, hipStream_t st) {
+  if (!d_weights || gr->n_entries == 0) return N2V_OK;
+  const uint32_t rb = gr->max_row_wsum <= 0xFFFFFFFFull ? 4u : 8u;
+  void* R = nullptr;
+  hipError_t e = hipMalloc(&R, (size_t)gr->n_entries * rb);
+  if (e != hipSuccess)
+    return fail(N2V_ERR_NOMEM, "hipMalloc prefix (%llu bytes): %s", (unsigned long long)(gr->n_entries * rb),
+                hipGetErrorString(e));
+  e = launch_row_prefix(d_offsets, gr->dev.n, d_weights, R, rb, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    hipFree(R);
+    return hip_fail(e, "row prefix");
   }
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    gr->handle = g_next_graph++;
-    g_graphs[gr->handle] = gr;
-  }
-  *out = gr->handle;
+  gr->dev.R = R;
+  gr->dev.r_bytes = rb;
+  gr->owned_bytes += gr->n_entries * rb;
   return N2V_OK;
+}
+
+n2v_graph register_graph(GraphRec* gr) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  gr->handle = g_next_graph++;
+  g_graphs[gr->handle] = gr;
+  return gr->handle;
+}
+
+void free_record(GraphRec* gr) {
+  if (gr->dev.R) hipFree(const_cast<void*>(gr->dev.R));
+  if (gr->neg_guide) hipFree(gr->neg_guide);
+  if (gr->ef_mem) hipFree(gr->ef_mem);
+  delete gr;
+}
+
+}  // namespace
+}  // namespace n2v
+
+extern "C" {
+
+int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst,
+                     uint64_t n_entries, const uint32_t* d_weights, uint32_t flags,
+                     void* hip_stream, n2v_graph* out) {
+  if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
+  *out = 0;
+  if (flags != 0) return fail(N2V_ERR_INVALID_ARG, "flags must be 0");
+  int rc = check_csr_args(d_offsets, n_nodes, d_dst, n_entries);
+  if (rc != N2V_OK) return rc;
+  DevInfo di;
+  rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  uint64_t h[4];
+  rc = validate_csr(d_offsets, n_nodes, d_dst, n_entries, d_weights, st, h);
+  if (rc != N2V_OK) return rc;
+  GraphRec* gr = new_record(n_nodes, n_entries, h, d_weights != nullptr, di.device);
+  gr->dev.O = d_offsets;
+  gr->dev.D = d_dst;
+  gr->dev.W = d_weights;
+  rc = build_prefix(gr, d_offsets, d_weights, st);
+  if (rc != N2V_OK) {
+    free_record(gr);
+    return rc;
+  }
+  *out = register_graph(gr);
+  return N2V_OK;
+}
+
+int n2v_graph_upload_ef(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t* d_dst,
+                        uint64_t n_entries, const uint32_t* d_weights, uint32_t quantum,
+                        void* hip_stream, n2v_graph* out) {
+  if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
+  *out = 0;
+  if (n_nodes == 0) return fail(N2V_ERR_INVALID_ARG, "an Elias-Fano graph needs at least one node");
+  if (quantum == 0) quantum = 256;
+  uint32_t lgq = 0;
+  while ((1u << lgq) < quantum) ++lgq;
+  if ((1u << lgq) != quantum || quantum < 8 || quantum > 65536)
+    return fail(N2V_ERR_INVALID_ARG, "quantum %u is not a power of two in [8, 65536]", quantum);
+  int rc = check_csr_args(d_offsets, n_nodes, d_dst, n_entries);
+  if (rc != N2V_OK) return rc;
+  DevInfo di;
+  rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  uint64_t h[4];
+  rc = validate_csr(d_offsets, n_nodes, d_dst, n_entries, d_weights, st, h);
+  if (rc != N2V_OK) return rc;
+  GraphRec* gr = new_record(n_nodes, n_entries, h, d_weights != nullptr, di.device);
+  gr->storage = N2V_STORAGE_EF;
+  gr->ef_quantum = quantum;
+  uint64_t hw, lw, n1, n0;
+  ef_shape((int64_t)n_nodes, n_entries, lgq, &gr->ef, &hw, &lw, &n1, &n0);
+  const uint64_t words = hw + lw + n1 + n0;
+  hipError_t e = hipMalloc(&gr->ef_mem, (size_t)(words ? words : 1) * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    free_record(gr);
+    return fail(N2V_ERR_NOMEM, "hipMalloc Elias-Fano store (%llu words): %s", (unsigned long long)words,
+                hipGetErrorString(e));
+  }
+  uint64_t* base = (uint64_t*)gr->ef_mem;
+  gr->ef.H = base;
+  gr->ef.L = base + hw;
+  gr->ef.S1 = base + hw + lw;
+  gr->ef.S0 = base + hw + lw + n1;
+  gr->owned_bytes += words * sizeof(uint64_t);
+  e = hipMemsetAsync(gr->ef_mem, 0, (size_t)(hw + lw) * sizeof(uint64_t), st);
+  if (e == hipSuccess) e = launch_ef_build(d_offsets, (int64_t)n_nodes, d_dst, gr->ef, di, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    free_record(gr);
+    return hip_fail(e, "Elias-Fano build");
+  }
+  rc = build_prefix(gr, d_offsets, d_weights, st);
+  if (rc != N2V_OK) {
+    free_record(gr);
+    return rc;
+  }
+  *out = register_graph(gr);
+  return N2V_OK;
+}
+
+int n2v_ef_info(n2v_graph g, n2v_ef_info_t* out) {
+  if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
+  GraphRec* gr = find_graph(g);
+  if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
+  if (gr->storage != N2V_STORAGE_EF) return fail(N2V_ERR_INVALID_ARG, "graph %llu is not an Elias-Fano graph",
+                                                 (unsigned long long)g);
+  uint64_t hw, lw, n1, n0;
+  EFDev tmp;
+  ef_shape(gr->dev.n, gr->n_entries, gr->ef.lgq, &tmp, &hw, &lw, &n1, &n0);
+  std::memset(out, 0, sizeof(*out));
+  out->k = gr->ef.k;
+  out->l = gr->ef.l;
+  out->quantum = gr->ef_quantum;
+  out->u = gr->ef.u;
+  out->n_codes = gr->ef.m;
+  out->n_zeros = gr->ef.n_zeros;
+  out->h_bits = gr->ef.h_bits;
+  out->h_words = hw;
+  out->l_words = lw;
+  out->s1_len = n1;
+  out->s0_len = n0;
+  out->d_H = gr->ef.H;
+  out->d_L = gr->ef.L;
+  out->d_S1 = gr->ef.S1;
+  out->d_S0 = gr->ef.S0;
+  return N2V_OK;
+}
+
+static int ef_bulk(n2v_graph g, const uint64_t* d_in, uint64_t count, uint64_t* d_out, void* hip_stream,
+                   bool select) {
+  GraphRec* gr = find_graph(g);
+  if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
+  if (gr->storage != N2V_STORAGE_EF) return fail(N2V_ERR_INVALID_ARG, "graph %llu is not an Elias-Fano graph",
+                                                 (unsigned long long)g);
+  if (count > 0 && (!d_in || !d_out)) return fail(N2V_ERR_INVALID_ARG, "arrays must be non-NULL");
+  DevInfo di;
+  int rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  hipError_t e = select ? launch_ef_select(gr->ef, d_in, count, d_out, di, (hipStream_t)hip_stream)
+                        : launch_ef_rank(gr->ef, d_in, count, d_out, di, (hipStream_t)hip_stream);
+  return e == hipSuccess ? N2V_OK : hip_fail(e, select ? "select launch" : "rank launch");
+}
+
+int n2v_ef_select(n2v_graph g, const uint64_t* d_idx, uint64_t count, uint64_t* d_out, void* hip_stream) {
+  return ef_bulk(g, d_idx, count, d_out, hip_stream, true);
+}
+
+int n2v_ef_rank(n2v_graph g, const uint64_t* d_x, uint64_t count, uint64_t* d_out, void* hip_stream) {
+  return ef_bulk(g, d_x, count, d_out, hip_stream, false);
 }
 
 int n2v_graph_info(n2v_graph g, n2v_graph_info_t* out) {
@@ -275,6 +427,8 @@ int n2v_graph_info(n2v_graph g, n2v_graph_info_t* out) {
   out->weighted = gr->weighted;
   out->prefix_bytes = gr->dev.r_bytes;
   out->device_bytes = gr->owned_bytes;
+  out->storage = gr->storage;
+  out->ef_quantum = gr->ef_quantum;
   return N2V_OK;
 }
 
@@ -287,9 +441,7 @@ int n2v_graph_release(n2v_graph g) {
     gr = it->second;
     g_graphs.erase(it);
   }
-  if (gr->dev.R) hipFree(const_cast<void*>(gr->dev.R));
-  if (gr->neg_guide) hipFree(gr->neg_guide);
-  delete gr;
+  free_record(gr);
   return N2V_OK;
 }
 
@@ -323,6 +475,11 @@ int n2v_negative_samples(n2v_graph g, const int32_t* d_walks, uint64_t n_walks, 
   if (rc != N2V_OK) return rc;
   if (di.device != gr->device) return fail(N2V_ERR_INVALID_ARG, "graph lives on device %d, current is %d", gr->device, di.device);
   hipStream_t st = (hipStream_t)hip_stream;
+  if (gr->storage == N2V_STORAGE_EF) {
+    hipError_t e = launch_negatives_ef(gr->ef, d_walks, n_walks, walk_len, n_neg, seed, walk_id_base, d_negatives,
+                                       di, st);
+    return e == hipSuccess ? N2V_OK : hip_fail(e, "negatives launch");
+  }
   int32_t* guide = nullptr;
   uint32_t shift = 0;
   if (gr->n_entries > 0) {
@@ -378,10 +535,16 @@ static int walks_common(n2v_graph g, uint32_t kind, const int32_t* d_starts, uin
   int rc = prepare_request(*gr, kind, d_starts, n_starts, walks_per_start, walk_len, p, q, seed,
                            walk_id_base, d_walks, d_lens, k_approx, &a, &path);
   if (rc != N2V_OK) return rc;
+  if (gr->storage == N2V_STORAGE_EF && k_approx > 0)
+    return fail(N2V_ERR_INVALID_ARG, "approximated walks need a CSR graph");
   if (a.nwalks == 0) return N2V_OK;
   DevInfo di;
   rc = current_devinfo(&di);
   if (rc != N2V_OK) return rc;
+  if (gr->storage == N2V_STORAGE_EF) {
+    hipError_t e = launch_walks_ef(a, path, gr->ef, di, (hipStream_t)hip_stream);
+    return e == hipSuccess ? N2V_OK : hip_fail(e, "walk launch");
+  }
   LaunchCfg cfg = choose_cfg(*gr, di);
   hipError_t e = launch_walks(a, path, cfg, di, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "walk launch");

@@ -14,20 +14,6 @@ namespace {
 constexpr uint32_t kCtxTile = 1024;  // positions per contexts tile
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
-// Walk position e = e0 + d split into (row, column) given e0 = row0 * L + i0.
-__device__ __forceinline__ void split_pos(uint64_t row0, uint32_t i0, uint64_t d, uint32_t L, uint64_t* row,
-                                          uint32_t* i) {
-  const uint64_t s = (uint64_t)i0 + d;
-  if (s < L) {
-    *row = row0;
-    *i = (uint32_t)s;
-  } else {
-    const uint64_t k = s / L;
-    *row = row0 + k;
-    *i = (uint32_t)(s - k * L);
-  }
-}
-
 // Contexts with the tile's walk words and a halo of H = min(window * stride,
 // L - 1) positions on each side in LDS (H small enough to fit).  Position p of
 // the tile sits at ys[H + p]; its column (or kNoNode when it holds no node) at

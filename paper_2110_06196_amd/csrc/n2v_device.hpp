@@ -146,6 +146,21 @@ __device__ __forceinline__ uint64_t grp_ballot(bool pred, int gbase) {
   return (m >> gbase) & ((1ull << G) - 1ull);
 }
 
+// Walk position e = e0 + d of a [rows][L] array split into (row, column),
+// given e0 = row0 * L + i0.
+__device__ __forceinline__ void split_pos(uint64_t row0, uint32_t i0, uint64_t d, uint32_t L, uint64_t* row,
+                                          uint32_t* i) {
+  const uint64_t s = (uint64_t)i0 + d;
+  if (s < L) {
+    *row = row0;
+    *i = (uint32_t)s;
+  } else {
+    const uint64_t k = s / L;
+    *row = row0 + k;
+    *i = (uint32_t)(s - k * L);
+  }
+}
+
 // First index j in [0, d) with R[j] > T (R non-decreasing); d if none.
 template <typename RT>
 __device__ __forceinline__ uint32_t upper_bound_gt(const RT* R, uint32_t d, uint64_t T) {

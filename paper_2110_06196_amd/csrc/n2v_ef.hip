@@ -1,0 +1,507 @@
+// Elias-Fano edge store on the GPU (Methods, "Edge Encoding", "Operations on
+// Elias-Fano", "Efficient implementation of Elias-Fano"): construction from a
+// CSR graph, select and rank, and every exact walk kind over the store.  Only
+// where the neighbours come from changes; the walks are the CSR walks, bit for
+// bit.
+//
+// Layout: edge code phi_k(a, b) = a 2^k + b, k = ceil(log2 n), u = n 2^k;
+// l = floor(log2(u / m)) low bits per code in L (field i = bits [i l, i l + l),
+// least significant first); the one of code i at bit (code_i >> l) + i of H,
+// ((u - 1) >> l) + 1 zeros; S1[j] / S0[j] = position of one / zero number
+// j 2^lgq.  rank(x) counts the codes strictly below x, so the row of node a is
+// [rank(phi(a, 0)), rank(phi(a + 1, 0))) and neighbour j of a is
+// select(rank(phi(a, 0)) + j) & (2^k - 1).
+#include "n2v_device.hpp"
+#include "n2v_internal.hpp"
+
+namespace n2v {
+namespace {
+
+// Bit position of set bit number r (from 0, least significant first) of b,
+// which has more than r set bits: a popcount bisection over halves.
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t b, uint32_t r) {
+  uint32_t pos = 0;
+  uint32_t c = (uint32_t)__popcll(b & 0xFFFFFFFFull);
+  if (r >= c) { r -= c; b >>= 32; pos += 32; }
+  c = (uint32_t)__popcll(b & 0xFFFFull);
+  if (r >= c) { r -= c; b >>= 16; pos += 16; }
+  c = (uint32_t)__popcll(b & 0xFFull);
+  if (r >= c) { r -= c; b >>= 8; pos += 8; }
+  c = (uint32_t)__popcll(b & 0xFull);
+  if (r >= c) { r -= c; b >>= 4; pos += 4; }
+  c = (uint32_t)__popcll(b & 0x3ull);
+  if (r >= c) { r -= c; b >>= 2; pos += 2; }
+  if (r >= (uint32_t)(b & 1ull)) pos += 1;
+  return pos;
+}
+
+__device__ __forceinline__ uint64_t ef_low(const EFDev& e, uint64_t i) {
+  if (e.l == 0) return 0;
+  const uint64_t bit = i * e.l;
+  const uint64_t w = bit >> 6;
+  const uint32_t o = (uint32_t)(bit & 63);
+  uint64_t v = e.L[w] >> o;
+  if (o + e.l > 64) v |= e.L[w + 1] << (64 - o);
+  return v & ((1ull << e.l) - 1);
+}
+
+// Position of one number i (i < m): from the sample of its quantum, count
+// ones word by word.
+__device__ __forceinline__ uint64_t ef_one_pos(const EFDev& e, uint64_t i) {
+  const uint64_t j = i >> e.lgq;
+  const uint64_t p = e.S1[j];
+  uint64_t r = i - (j << e.lgq);
+  uint64_t w = p >> 6;
+  uint64_t b = e.H[w] & (~0ull << (p & 63));
+  while (true) {
+    const uint32_t c = (uint32_t)__popcll(b);
+    if (r < c) break;
+    r -= c;
+    b = e.H[++w];
+  }
+  return (w << 6) + nth_set_bit(b, (uint32_t)r);
+}
+
+// Position of zero number z (z < n_zeros).
+__device__ __forceinline__ uint64_t ef_zero_pos(const EFDev& e, uint64_t z) {
+  const uint64_t j = z >> e.lgq;
+  const uint64_t p = e.S0[j];
+  uint64_t r = z - (j << e.lgq);
+  uint64_t w = p >> 6;
+  uint64_t b = ~e.H[w] & (~0ull << (p & 63));
+  while (true) {
+    const uint32_t c = (uint32_t)__popcll(b);
+    if (r < c) break;
+    r -= c;
+    b = ~e.H[++w];
+  }
+  return (w << 6) + nth_set_bit(b, (uint32_t)r);
+}
+
+// select(i): the i-th smallest code (i < m).
+__device__ __forceinline__ uint64_t ef_select(const EFDev& e, uint64_t i) {
+  return ((ef_one_pos(e, i) - i) << e.l) | ef_low(e, i);
+}
+
+// rank(x): codes strictly below x.  Codes with high part below hx = x >> l
+// are the ones before zero number hx - 1; those with high part hx follow it
+// and are compared by their low parts.
+__device__ __forceinline__ uint64_t ef_rank(const EFDev& e, uint64_t x) {
+  if (e.m == 0) return 0;
+  const uint64_t hx = x >> e.l;
+  if (hx >= e.n_zeros) return e.m;
+  uint64_t i = 0, p = 0;
+  if (hx > 0) {
+    const uint64_t p0 = ef_zero_pos(e, hx - 1);
+    i = p0 - (hx - 1);
+    p = p0 + 1;
+  }
+  const uint64_t xl = e.l ? (x & ((1ull << e.l) - 1)) : 0;
+  while (i < e.m && ((e.H[p >> 6] >> (p & 63)) & 1ull) && ef_low(e, i) < xl) {
+    ++i;
+    ++p;
+  }
+  return i;
+}
+
+__device__ __forceinline__ int32_t ef_nbr(const EFDev& e, uint64_t idx) {
+  return (int32_t)(ef_select(e, idx) & ((1ull << e.k) - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Construction from a validated CSR.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kEfChunk = 4096;
+
+// Last a in [alo, ahi] with O[a] <= i (rows may be empty), given O[alo] <= i.
+__device__ __forceinline__ int64_t src_of(const uint64_t* __restrict__ O, int64_t alo, int64_t ahi, uint64_t i) {
+  while (alo < ahi) {
+    const int64_t mid = alo + ((ahi - alo + 1) >> 1);
+    if (O[mid] <= i) alo = mid;
+    else ahi = mid - 1;
+  }
+  return alo;
+}
+
+// Every entry sets its bit of H and ORs its low part into L (both zeroed).
+// A block takes a chunk of entries and narrows the source search to the
+// rows the chunk spans.
+__global__ __launch_bounds__(256) void k_ef_fill(const uint64_t* __restrict__ O, int64_t n,
+                                                 const int32_t* __restrict__ D, EFDev e, uint64_t* H, uint64_t* L) {
+  __shared__ int64_t rows[2];
+  for (uint64_t e0 = (uint64_t)blockIdx.x * kEfChunk; e0 < e.m; e0 += (uint64_t)gridDim.x * kEfChunk) {
+    const uint64_t e1 = e0 + kEfChunk < e.m ? e0 + kEfChunk : e.m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      rows[0] = src_of(O, 0, n - 1, e0);
+      rows[1] = src_of(O, 0, n - 1, e1 - 1);
+    }
+    __syncthreads();
+    const int64_t a0 = rows[0], a1 = rows[1];
+    for (uint64_t i = e0 + threadIdx.x; i < e1; i += 256) {
+      const int64_t a = src_of(O, a0, a1, i);
+      const uint64_t code = ((uint64_t)a << e.k) | (uint64_t)(uint32_t)D[i];
+      const uint64_t p = (code >> e.l) + i;
+      atomicOr((unsigned long long*)&H[p >> 6], 1ull << (p & 63));
+      if (e.l) {
+        const uint64_t low = code & ((1ull << e.l) - 1);
+        const uint64_t bit = i * e.l;
+        const uint64_t w = bit >> 6;
+        const uint32_t o = (uint32_t)(bit & 63);
+        atomicOr((unsigned long long*)&L[w], low << o);
+        if (o + e.l > 64) atomicOr((unsigned long long*)&L[w + 1], low >> (64 - o));
+      }
+    }
+  }
+}
+
+// Quantum indexes, straight from the CSR: one number i sits at
+// (code_i >> l) + i; zero number z sits after the codes whose high part is at
+// most z, i.e. at z + #{codes < (z + 1) 2^l}.
+__global__ __launch_bounds__(256) void k_ef_index(const uint64_t* __restrict__ O, int64_t n,
+                                                  const int32_t* __restrict__ D, EFDev e, uint64_t s1_len,
+                                                  uint64_t s0_len, uint64_t* S1, uint64_t* S0) {
+  const uint64_t kmask = (1ull << e.k) - 1;
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < s1_len + s0_len;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    if (j < s1_len) {
+      const uint64_t i = j << e.lgq;
+      const int64_t a = src_of(O, 0, n - 1, i);
+      const uint64_t code = ((uint64_t)a << e.k) | (uint64_t)(uint32_t)D[i];
+      S1[j] = (code >> e.l) + i;
+    } else {
+      const uint64_t z = (j - s1_len) << e.lgq;
+      const uint64_t y = (z + 1) << e.l;
+      const uint64_t a = y >> e.k;
+      uint64_t c = e.m;
+      if (a < (uint64_t)n) {
+        const uint64_t lo = O[a];
+        c = lo + lower_bound_i32(D + lo, (uint32_t)(O[a + 1] - lo), (int32_t)(y & kmask));
+      }
+      S0[j - s1_len] = z + c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ef_select_bulk(EFDev e, const uint64_t* __restrict__ idx, uint64_t count,
+                                                        uint64_t* __restrict__ out) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (uint64_t)gridDim.x * blockDim.x)
+    out[t] = idx[t] < e.m ? ef_select(e, idx[t]) : ~0ull;
+}
+
+__global__ __launch_bounds__(256) void k_ef_rank_bulk(EFDev e, const uint64_t* __restrict__ x, uint64_t count,
+                                                      uint64_t* __restrict__ out) {
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (uint64_t)gridDim.x * blockDim.x)
+    out[t] = ef_rank(e, x[t]);
+}
+
+// ---------------------------------------------------------------------------
+// Walks.  The arithmetic is that of the CSR kernels; the row of v is
+// [rank(phi(v, 0)), rank(phi(v + 1, 0))), weights are differences of the row
+// prefix R, and t is found in N(v) by rank(phi(v, t)).
+// ---------------------------------------------------------------------------
+enum { kEfFoUnw = 0, kEfFoW = 1, kEfRetUnw = 2, kEfRetW = 3 };
+
+template <typename RT>
+__device__ __forceinline__ uint64_t weight_at(const RT* __restrict__ R, uint64_t lo, uint32_t j) {
+  const uint64_t hi = (uint64_t)R[lo + j];
+  return j ? hi - (uint64_t)R[lo + j - 1] : hi;
+}
+
+template <int MODE, typename RT>
+__device__ __forceinline__ void lane_walk_ef(const WalkArgs& a, const EFDev& e, uint64_t w) {
+  const RT* __restrict__ R = (const RT*)a.g.R;
+  int32_t* __restrict__ row = a.Y + w * a.L;
+  const int32_t start = a.starts[w % a.ns];
+  const uint64_t wid = a.wid_base + w;
+  uint32_t len = 0;
+  if (start >= 0 && (int64_t)start < a.g.n) {
+    row[0] = start;
+    len = 1;
+    int32_t v = start, t = -1;
+    uint64_t lo = ef_rank(e, (uint64_t)v << e.k);
+    for (uint32_t s = 1; s < a.L; ++s) {
+      const uint32_t d = (uint32_t)(ef_rank(e, ((uint64_t)v + 1) << e.k) - lo);
+      if (d == 0) break;  // dead end
+      const uint64_t r = philox_draw(a.seed, s, wid);
+      uint32_t j;
+      if (MODE == kEfFoUnw || (MODE == kEfRetUnw && t < 0)) {
+        j = (uint32_t)scale_draw(r, d);
+      } else if (MODE == kEfFoW || (MODE == kEfRetW && t < 0)) {
+        const uint64_t total = (uint64_t)R[lo + d - 1];
+        if (total == 0) break;
+        j = upper_bound_gt(R + lo, d, scale_draw(r, total));
+      } else {
+        const uint64_t tc = ((uint64_t)v << e.k) | (uint64_t)(uint32_t)t;
+        const uint64_t rt = ef_rank(e, tc);
+        const uint32_t pt = (uint32_t)(rt - lo);  // entries of N(v) below t
+        const bool has_t = pt < d && ef_select(e, rt) == tc;
+        uint64_t wt = 0;
+        if (has_t) wt = (MODE == kEfRetW) ? weight_at(R, lo, pt) : 1ull;
+        const uint64_t S = (MODE == kEfRetW) ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
+        const uint64_t corr = ((uint64_t)a.P16 - (uint64_t)kC16) * wt;  // mod 2^64
+        const uint64_t total = (uint64_t)kC16 * S + corr;
+        if (total == 0) break;
+        const uint64_t T = scale_draw(r, total);
+        uint32_t jl = 0, jh = d - 1;
+        while (jl < jh) {
+          const uint32_t mid = jl + ((jh - jl) >> 1);
+          const uint64_t Rm = (MODE == kEfRetW) ? (uint64_t)R[lo + mid] : (uint64_t)(mid + 1);
+          const uint64_t Bm = (uint64_t)kC16 * Rm + (mid >= pt ? corr : 0ull);
+          if (Bm > T) jh = mid;
+          else jl = mid + 1;
+        }
+        j = jl;
+      }
+      const int32_t x = ef_nbr(e, lo + j);
+      row[s] = x;
+      len = s + 1;
+      t = v;
+      v = x;
+      lo = ef_rank(e, (uint64_t)v << e.k);
+    }
+  }
+  for (uint32_t s = len; s < a.L; ++s) row[s] = -1;
+  if (a.lens) a.lens[w] = (int32_t)len;
+  if (a.steps && len > 1) atomicAdd(a.steps, (unsigned long long)(len - 1));
+}
+
+template <int MODE, typename RT>
+__global__ __launch_bounds__(256) void k_walk_lane_ef(WalkArgs a, EFDev e) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwalks; w += stride)
+    lane_walk_ef<MODE, RT>(a, e, w);
+}
+
+// node2vec with 1/q != 1: one wavefront per walk, two passes over the biased
+// weights of N(v) (block sums, then a scan of the block holding the draw);
+// membership of a candidate x in N(t) is rank(phi(t, x)) landing on x.
+template <bool WEIGHTED, typename RT>
+__device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, uint64_t w, int gl) {
+  constexpr int G = 64;
+  const RT* __restrict__ R = (const RT*)a.g.R;
+  const uint64_t P16 = a.P16, Q16 = a.Q16;
+  int32_t* __restrict__ row = a.Y + w * a.L;
+  const int32_t start = a.starts[w % a.ns];
+  const uint64_t wid = a.wid_base + w;
+  uint32_t len = 0;
+  if (start >= 0 && (int64_t)start < a.g.n) {
+    if (gl == 0) row[0] = start;
+    len = 1;
+    int32_t v = start, t = -1;
+    uint64_t lo = ef_rank(e, (uint64_t)v << e.k);
+    for (uint32_t s = 1; s < a.L; ++s) {
+      const uint32_t d = (uint32_t)(ef_rank(e, ((uint64_t)v + 1) << e.k) - lo);
+      if (d == 0) break;
+      const uint64_t r = philox_draw(a.seed, s, wid);
+      uint32_t jsel = d;
+      if (!a.second_order || t < 0) {
+        const uint64_t S = WEIGHTED ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
+        if (S == 0) break;
+        const uint64_t T = scale_draw(r, S);
+        jsel = WEIGHTED ? upper_bound_gt(R + lo, d, T) : (uint32_t)T;
+      } else {
+        const uint64_t tc0 = (uint64_t)t << e.k;
+        auto bias = [&](uint32_t j) -> uint64_t {
+          const int32_t x = ef_nbr(e, lo + j);
+          const uint64_t wt = WEIGHTED ? weight_at(R, lo, j) : 1ull;
+          if (x == t) return wt * P16;
+          const uint64_t c = tc0 | (uint64_t)(uint32_t)x;
+          const uint64_t rk = ef_rank(e, c);
+          return wt * ((rk < e.m && ef_select(e, rk) == c) ? (uint64_t)kC16 : Q16);
+        };
+        const uint32_t nc = (d + G - 1) / G;
+        const uint32_t bs = (nc + G - 1) / G;
+        uint64_t acc = 0, blk = 0;
+        for (uint32_t c = 0; c < nc; ++c) {
+          const uint32_t j = c * G + (uint32_t)gl;
+          if (j < d) acc += bias(j);
+          if ((c + 1) % bs == 0 || c + 1 == nc) {
+            const uint64_t sb = grp_sum<G>(acc);
+            if ((uint32_t)gl == c / bs) blk = sb;
+            acc = 0;
+          }
+        }
+        const uint64_t incl = grp_incl_scan<G>(blk, gl);
+        const uint64_t total = grp_bcast<G>(incl, G - 1);
+        if (total == 0) break;
+        const uint64_t T = scale_draw(r, total);
+        const uint64_t bm = grp_ballot<G>(incl > T, 0);
+        const int kb = __ffsll((unsigned long long)bm) - 1;
+        uint64_t base = grp_bcast<G>(incl - blk, kb);
+        const uint32_t cend = min((uint32_t)(kb + 1) * bs, nc);
+        for (uint32_t c = (uint32_t)kb * bs; c < cend; ++c) {
+          const uint32_t j = c * G + (uint32_t)gl;
+          const uint64_t b = j < d ? bias(j) : 0ull;
+          const uint64_t inc = grp_incl_scan<G>(b, gl);
+          const uint64_t m2 = grp_ballot<G>(base + inc > T, 0);
+          if (m2) {
+            jsel = c * G + (uint32_t)(__ffsll((unsigned long long)m2) - 1);
+            break;
+          }
+          base += grp_bcast<G>(inc, G - 1);
+        }
+      }
+      if (jsel >= d) break;  // unreachable: the draw lies below the total
+      const int32_t x = ef_nbr(e, lo + jsel);
+      if (gl == 0) row[s] = x;
+      len = s + 1;
+      t = v;
+      v = x;
+      lo = ef_rank(e, (uint64_t)v << e.k);
+    }
+  }
+  for (uint32_t s = len + (uint32_t)gl; s < a.L; s += G) row[s] = -1;
+  if (gl == 0) {
+    if (a.lens) a.lens[w] = (int32_t)len;
+    if (a.steps && len > 1) atomicAdd(a.steps, (unsigned long long)(len - 1));
+  }
+}
+
+template <bool WEIGHTED, typename RT>
+__global__ __launch_bounds__(256) void k_walk_n2v_ef(WalkArgs a, EFDev e) {
+  const int gl = threadIdx.x & 63;
+  const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+  for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; w < a.nwalks; w += waves)
+    wave_walk_ef<WEIGHTED, RT>(a, e, w, gl);
+}
+
+// Scale-free negatives: the node owning entry T of the edge list is the
+// source of code T, select(T) >> k.  Same tiles and counters as the CSR form.
+__global__ __launch_bounds__(256) void k_negatives_ef(EFDev e, const int32_t* __restrict__ Y, uint64_t n_pos,
+                                                      uint32_t L, uint32_t n_neg, uint32_t lgP, uint64_t seed,
+                                                      uint64_t wid_base, int32_t* __restrict__ N) {
+  extern __shared__ int32_t sm[];  // [P * n_neg]
+  const uint32_t P = 1u << lgP;
+  const uint32_t npairs = (n_neg + 1u) / 2u;
+  const uint32_t t = threadIdx.x;
+  for (uint64_t e0 = (uint64_t)blockIdx.x * P; e0 < n_pos; e0 += (uint64_t)gridDim.x * P) {
+    const uint32_t np = (uint32_t)(n_pos - e0 < P ? n_pos - e0 : P);
+    const uint64_t row0 = e0 / L;
+    const uint32_t i0 = (uint32_t)(e0 - row0 * L);
+    __syncthreads();
+    for (uint32_t it = t; it < P * npairs; it += 256) {
+      const uint32_t pos = it & (P - 1u), jp = it >> lgP;
+      if (pos >= np) continue;
+      int32_t v0 = -1, v1 = -1;
+      if (e.m > 0 && Y[e0 + pos] >= 0) {
+        uint64_t row;
+        uint32_t i;
+        split_pos(row0, i0, pos, L, &row, &i);
+        const uint64_t wid = wid_base + row;
+        uint32_t wd[4];
+        philox_words(seed, i, (uint32_t)wid, (uint32_t)(wid >> 32), 0x80000000u + jp, wd);
+        v0 = (int32_t)(ef_select(e, scale_draw((uint64_t)wd[0] | ((uint64_t)wd[1] << 32), e.m)) >> e.k);
+        if (2u * jp + 1u < n_neg)
+          v1 = (int32_t)(ef_select(e, scale_draw((uint64_t)wd[2] | ((uint64_t)wd[3] << 32), e.m)) >> e.k);
+      }
+      sm[pos * n_neg + 2u * jp] = v0;
+      if (2u * jp + 1u < n_neg) sm[pos * n_neg + 2u * jp + 1u] = v1;
+    }
+    __syncthreads();
+    int32_t* __restrict__ out = N + e0 * n_neg;
+    for (uint32_t x = t; x < np * n_neg; x += 256) out[x] = sm[x];
+  }
+}
+
+int ef_blocks(uint64_t items, const DevInfo& di) {
+  const uint64_t want = (items + 255) / 256;
+  const uint64_t cap = (uint64_t)(di.cus > 0 ? di.cus : 256) * 16;
+  return (int)(want < cap ? (want ? want : 1) : cap);
+}
+
+}  // namespace
+
+void ef_shape(int64_t n, uint64_t m, uint32_t lgq, EFDev* e, uint64_t* h_words, uint64_t* l_words,
+              uint64_t* s1_len, uint64_t* s0_len) {
+  uint32_t k = 0;
+  while ((1ll << k) < n) ++k;
+  e->k = k;
+  e->u = (uint64_t)n << k;
+  e->m = m;
+  uint32_t l = 0;
+  if (m > 0) {
+    const uint64_t ratio = e->u / m;
+    while (l < 63 && (ratio >> (l + 1)) > 0) ++l;
+  }
+  e->l = l;
+  e->lgq = lgq;
+  e->n_zeros = ((e->u - 1) >> l) + 1;
+  e->h_bits = m + e->n_zeros;
+  *h_words = (e->h_bits + 63) / 64;
+  *l_words = (m * l + 63) / 64;
+  *s1_len = (m + (1ull << lgq) - 1) >> lgq;
+  *s0_len = (e->n_zeros + (1ull << lgq) - 1) >> lgq;
+}
+
+hipError_t launch_ef_build(const uint64_t* O, int64_t n, const int32_t* D, const EFDev& e, const DevInfo& di,
+                           hipStream_t st) {
+  uint64_t hw, lw, n1, n0;
+  EFDev tmp;
+  ef_shape(n, e.m, e.lgq, &tmp, &hw, &lw, &n1, &n0);
+  if (e.m > 0) {
+    hipLaunchKernelGGL(k_ef_fill, dim3(ef_blocks((e.m + kEfChunk - 1) / kEfChunk * 256, di)), dim3(256), 0, st, O,
+                       n, D, e, const_cast<uint64_t*>(e.H), const_cast<uint64_t*>(e.L));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(k_ef_index, dim3(ef_blocks(n1 + n0, di)), dim3(256), 0, st, O, n, D, e, n1, n0,
+                     const_cast<uint64_t*>(e.S1), const_cast<uint64_t*>(e.S0));
+  return hipGetLastError();
+}
+
+hipError_t launch_ef_select(const EFDev& e, const uint64_t* idx, uint64_t count, uint64_t* out, const DevInfo& di,
+                            hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ef_select_bulk, dim3(ef_blocks(count, di)), dim3(256), 0, st, e, idx, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ef_rank(const EFDev& e, const uint64_t* x, uint64_t count, uint64_t* out, const DevInfo& di,
+                          hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ef_rank_bulk, dim3(ef_blocks(count, di)), dim3(256), 0, st, e, x, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_walks_ef(const WalkArgs& a, Path path, const EFDev& e, const DevInfo& di, hipStream_t st) {
+  if (a.nwalks == 0) return hipSuccess;
+  const bool weighted = a.g.R != nullptr;
+  const bool r64 = a.g.r_bytes == 8;
+  const dim3 lane_grid(ef_blocks(a.nwalks, di));
+  switch (path) {
+    case Path::kFirstOrder:
+      if (!weighted) hipLaunchKernelGGL((k_walk_lane_ef<kEfFoUnw, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
+      else if (r64) hipLaunchKernelGGL((k_walk_lane_ef<kEfFoW, uint64_t>), lane_grid, dim3(256), 0, st, a, e);
+      else hipLaunchKernelGGL((k_walk_lane_ef<kEfFoW, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
+      break;
+    case Path::kReturnOnly:
+      if (!weighted) hipLaunchKernelGGL((k_walk_lane_ef<kEfRetUnw, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
+      else if (r64) hipLaunchKernelGGL((k_walk_lane_ef<kEfRetW, uint64_t>), lane_grid, dim3(256), 0, st, a, e);
+      else hipLaunchKernelGGL((k_walk_lane_ef<kEfRetW, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
+      break;
+    default: {
+      const dim3 wave_grid(ef_blocks(a.nwalks * 64, di));
+      if (!weighted) hipLaunchKernelGGL((k_walk_n2v_ef<false, uint32_t>), wave_grid, dim3(256), 0, st, a, e);
+      else if (r64) hipLaunchKernelGGL((k_walk_n2v_ef<true, uint64_t>), wave_grid, dim3(256), 0, st, a, e);
+      else hipLaunchKernelGGL((k_walk_n2v_ef<true, uint32_t>), wave_grid, dim3(256), 0, st, a, e);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_negatives_ef(const EFDev& e, const int32_t* Y, uint64_t n_walks, uint32_t L, uint32_t n_neg,
+                               uint64_t seed, uint64_t wid_base, int32_t* N, const DevInfo& di, hipStream_t st) {
+  const uint64_t n_pos = n_walks * L;
+  if (n_pos == 0) return hipSuccess;
+  constexpr size_t kLds = 64 * 1024;
+  if ((size_t)n_neg * sizeof(int32_t) > kLds) return hipErrorInvalidValue;
+  uint32_t lgP = 8;
+  while (lgP > 0 && ((size_t)n_neg << lgP) * sizeof(int32_t) > kLds) --lgP;
+  const size_t lds = ((size_t)n_neg << lgP) * sizeof(int32_t);
+  hipLaunchKernelGGL(k_negatives_ef, dim3(ef_blocks(((n_pos + (1u << lgP) - 1) >> lgP) * 256, di)), dim3(256), lds,
+                     st, e, Y, n_pos, L, n_neg, lgP, seed, wid_base, N);
+  return hipGetLastError();
+}
+
+}  // namespace n2v

@@ -91,6 +91,33 @@ hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D,
 hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,
                              uint32_t r_bytes, hipStream_t st);
 
+// Elias-Fano edge store (n2v_ef.hip): the edge codes phi_k(a, b) = a 2^k + b
+// of the CSR entries, l low bits each in L, high parts as inverted unary gaps
+// in H (the one of element i is bit (code_i >> l) + i), and quantum indexes
+// S1[j] / S0[j] = position of one / zero number j 2^lgq.
+struct EFDev {
+  const uint64_t* H = nullptr;
+  const uint64_t* L = nullptr;
+  const uint64_t* S1 = nullptr;
+  const uint64_t* S0 = nullptr;
+  uint32_t k = 0, l = 0, lgq = 0, pad = 0;
+  uint64_t u = 0, m = 0, n_zeros = 0, h_bits = 0;
+};
+// Shape of the edge list of a graph on n >= 1 nodes with m entries.
+void ef_shape(int64_t n, uint64_t m, uint32_t lgq, EFDev* e, uint64_t* h_words, uint64_t* l_words,
+              uint64_t* s1_len, uint64_t* s0_len);
+// Fill H, L (zeroed by the caller), S1, S0 of `e` from a validated CSR.
+hipError_t launch_ef_build(const uint64_t* O, int64_t n, const int32_t* D, const EFDev& e, const DevInfo& di,
+                           hipStream_t st);
+hipError_t launch_ef_select(const EFDev& e, const uint64_t* idx, uint64_t count, uint64_t* out, const DevInfo& di,
+                            hipStream_t st);
+hipError_t launch_ef_rank(const EFDev& e, const uint64_t* x, uint64_t count, uint64_t* out, const DevInfo& di,
+                          hipStream_t st);
+// Walks over the Elias-Fano store (a.g.R holds the row prefix of weighted graphs).
+hipError_t launch_walks_ef(const WalkArgs& a, Path path, const EFDev& e, const DevInfo& di, hipStream_t st);
+hipError_t launch_negatives_ef(const EFDev& e, const int32_t* Y, uint64_t n_walks, uint32_t L, uint32_t n_neg,
+                               uint64_t seed, uint64_t wid_base, int32_t* N, const DevInfo& di, hipStream_t st);
+
 // Training corpora (n2v_corpus.hip).
 hipError_t launch_contexts(const int32_t* Y, uint64_t n_walks, uint32_t L, uint32_t window, uint32_t stride,
                            int32_t* C, const DevInfo& di, hipStream_t st);

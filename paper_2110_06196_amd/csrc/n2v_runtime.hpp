@@ -22,6 +22,10 @@ struct GraphRec {
   int device = 0;
   int32_t* neg_guide = nullptr;  // built on the first negative-sampling call
   uint32_t neg_shift = 0;
+  uint32_t storage = N2V_STORAGE_CSR;
+  EFDev ef;                  // Elias-Fano store (storage == N2V_STORAGE_EF)
+  void* ef_mem = nullptr;    // owned: H, L, S1, S0
+  uint32_t ef_quantum = 0;
 };
 
 extern thread_local std::string t_err;

@@ -53,6 +53,7 @@ int prepare_all(const n2v_request_desc_t* reqs, uint32_t n, std::vector<Prepared
     const n2v_request_desc_t& r = reqs[i];
     GraphRec* gr = find_graph(r.graph);
     if (!gr) return fail(N2V_ERR_BAD_HANDLE, "request %u: unknown graph", i);
+    if (gr->storage != N2V_STORAGE_CSR) return fail(N2V_ERR_INVALID_ARG, "request %u: batches need a CSR graph", i);
     Prepared p;
     Path path;
     int rc = prepare_request(*gr, r.kind, r.d_starts, r.n_starts, r.walks_per_start, r.walk_len, r.p,
@@ -696,6 +697,7 @@ int n2v_server_add_graph(n2v_server sh, n2v_graph g) {
   if (!s) return fail(N2V_ERR_BAD_HANDLE, "unknown server");
   GraphRec* gr = find_graph(g);
   if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph");
+  if (gr->storage != N2V_STORAGE_CSR) return fail(N2V_ERR_INVALID_ARG, "servers need a CSR graph");
   std::lock_guard<std::mutex> lk(s->mu);
   if (std::find(s->graphs.begin(), s->graphs.end(), gr) == s->graphs.end()) s->graphs.push_back(gr);
   return N2V_OK;
@@ -709,6 +711,7 @@ int n2v_request_submit(n2v_server sh, const n2v_request_desc_t* desc, uint64_t a
   if (!s) return fail(N2V_ERR_BAD_HANDLE, "unknown server");
   GraphRec* gr = find_graph(desc->graph);
   if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph");
+  if (gr->storage != N2V_STORAGE_CSR) return fail(N2V_ERR_INVALID_ARG, "servers need a CSR graph");
   if (desc->n_starts > 0 && !desc->d_starts) return fail(N2V_ERR_INVALID_ARG, "starts is NULL");
   if (desc->walk_len == 0 || desc->walks_per_start == 0) return fail(N2V_ERR_INVALID_ARG, "empty walk shape");
   if ((unsigned __int128)desc->n_starts * desc->walks_per_start * desc->walk_len >= ((unsigned __int128)1 << 60))

@@ -57,6 +57,15 @@ def test_argument_validation_without_device():
     assert L.n2v_set_tuning(ctypes.byref(bad)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_set_tuning(None) == n2v.N2V_OK
     assert L.n2v_walks_batched(None, 3, None) == n2v.N2V_ERR_INVALID_ARG
+    # Elias-Fano graphs: argument checks come before any device call
+    assert L.n2v_graph_upload_ef(None, 1, None, 0, None, 0, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
+    assert L.n2v_graph_upload_ef(ctypes.c_void_p(8), 0, None, 0, None, 0, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
+    for q in (4, 7, 100, 1 << 17):
+        assert L.n2v_graph_upload_ef(ctypes.c_void_p(8), 1, None, 0, None, q, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
+    ef = n2v.EFInfo()
+    assert L.n2v_ef_info(999, ctypes.byref(ef)) == n2v.N2V_ERR_BAD_HANDLE
+    assert L.n2v_ef_select(999, None, 0, None, None) == n2v.N2V_ERR_BAD_HANDLE
+    assert L.n2v_ef_rank(999, None, 0, None, None) == n2v.N2V_ERR_BAD_HANDLE
 
 
 def test_product_has_no_oracle_dependency():
