@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--runs", default="1,1;0.25,4", help="(p,q) pairs, ';'-separated")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--walk-len", type=int, default=100)
-    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served", "big", "corpus"],
+    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served", "big", "corpus", "ef"],
                     help="chung_lu_1m: plain launches (default); batched: 64 graphs x 4096 requests, one "
                          "launch per request vs one persistent hipGraph launch; served: the same requests "
                          "under Poisson arrivals, server vs one launch per request")
@@ -310,6 +310,9 @@ def main():
         return
     if args.config == "corpus":
         bench_corpus(args)
+        return
+    if args.config == "ef":
+        bench_ef(args)
         return
     import torch
     import paper_2110_06196_amd as n2v
@@ -873,6 +876,85 @@ def bench_corpus(args):
            "kernel_source_hash": kernel_source_hash(CORPUS_SOURCES)}
     print(json.dumps(out), flush=True)
     n2v.n2v_graph_release(g)
+
+
+def bench_ef(args):
+    """The 1M-node workload on the Elias-Fano store (quantum 256) next to the
+    CSR store: device bytes of each, first-order / node2vec (1, 1) walks (10
+    per node) and node2vec (0.25, 4) walks (1 per node), 100 slots, seed 42.
+    Every EF walk equals the CSR walk of the same request (checked in full)
+    and sampled rows equal the oracle."""
+    import torch
+    import oracle
+    import paper_2110_06196_amd as n2v
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    O, D, W = graph_cache()
+    n = len(O) - 1
+    Ot = torch.from_numpy(O.view(np.int64)).to(dev)
+    Dt = torch.from_numpy(D).to(dev)
+    Wt = torch.from_numpy(W.view(np.int32)).to(dev)
+    gc = n2v.n2v_graph_upload(Ot, Dt, Wt)
+    t0 = time.perf_counter()
+    ge = n2v.n2v_graph_upload_ef(Ot, Dt, Wt, 256)
+    t_build = time.perf_counter() - t0
+    ic, ie, ef = n2v.n2v_graph_info(gc), n2v.n2v_graph_info(ge), n2v.n2v_ef_info(ge)
+    ef_bytes = 8 * (ef["h_words"] + ef["l_words"] + ef["s1_len"] + ef["s0_len"])
+    csr_bytes = 8 * (n + 1) + 4 * D.size
+    prefix_bytes = ic["device_bytes"]
+    L, seed = args.walk_len, 42
+    deg = (Ot[1:] - Ot[:-1]).to(torch.int64)
+    S = torch.arange(n, dtype=torch.int32, device=dev)
+    runs = []
+    for (p, q, R) in [(1.0, 1.0, args.reps), (0.25, 4.0, 1)]:
+        nw = n * R
+        outs = {}
+        for name, g in (("csr", gc), ("ef", ge)):
+            Y = torch.empty((nw, L), dtype=torch.int32, device=dev)
+            lens = torch.empty(nw, dtype=torch.int32, device=dev)
+            ms = []
+            for k in range(args.warmup + args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                n2v.n2v_walks_node2vec(g, S, R, L, p, q, seed, 0, Y, lens)
+                e1.record()
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    ms.append(e0.elapsed_time(e1))
+            outs[name] = (Y, lens, float(np.mean(ms)))
+            print(f"[bench] ef: {name} p={p} q={q} {np.mean(ms):.1f} ms", file=sys.stderr, flush=True)
+        same = bool(torch.equal(outs["csr"][0], outs["ef"][0]) and torch.equal(outs["csr"][1], outs["ef"][1]))
+        Y, lens, ms = outs["ef"]
+        variant = "generic" if q != 1.0 else "fo_weighted"
+        steps, alg = algorithmic_bytes(torch, Y, lens, deg, variant)
+        rows = np.linspace(0, nw - 1, 200).astype(np.int64)
+        Yo, lo = oracle.walks_threaded(O, D, W, np.arange(n, dtype=np.int32), R, L, oracle.NODE2VEC, p, q, seed, 0,
+                                       rows, min(16, os.cpu_count() or 1))
+        idx = torch.from_numpy(rows).to(dev)
+        mism = int(((Y.index_select(0, idx).cpu().numpy() != Yo).any(1) |
+                    (lens.index_select(0, idx).cpu().numpy() != lo)).sum())
+        runs.append({"p": p, "q": q, "walks_per_node": R, "steps": steps, "ef_ms": ms, "csr_ms": outs["csr"][2],
+                     "ef_steps_per_s": steps / (ms / 1e3), "csr_steps_per_s": steps / (outs["csr"][2] / 1e3),
+                     "ef_alg_GBps": alg / (ms / 1e3) / 1e9, "ef_equals_csr": same,
+                     "oracle_sample_mismatching_rows": mism})
+    dom = runs[-1]
+    out = {"metric": METRIC, "value": dom["ef_steps_per_s"], "unit": "walk steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dom["ef_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "node2vec on the Elias-Fano store (quantum 256) of the Chung-Lu 1M-node graph, "
+                                  "100 slots, seed 42", "n_entries": int(D.size)},
+           "storage": {"csr_topology_bytes": csr_bytes, "ef_topology_bytes": ef_bytes,
+                       "ef_bits_per_entry": 8 * ef_bytes / max(1, D.size), "weight_prefix_bytes": prefix_bytes,
+                       "ef_k": ef["k"], "ef_l": ef["l"], "ef_build_s": t_build,
+                       "ef_bound_bits": 2 * D.size + D.size * int(np.ceil(np.log2(ef["u"] / D.size)))},
+           "roofline": {"bound": "hbm", "achieved": dom["ef_alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": dom["ef_alg_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "node2vec p=0.25 q=4 over Elias-Fano (the CSR step's algorithmic bytes)"},
+           "runs": runs, "kernel_source_hash": kernel_source_hash(("n2v_ef.hip", "n2v_device.hpp", "n2v_internal.hpp"))}
+    print(json.dumps(out), flush=True)
+    n2v.n2v_graph_release(ge)
+    n2v.n2v_graph_release(gc)
 
 
 if __name__ == "__main__":

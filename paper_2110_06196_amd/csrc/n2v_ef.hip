@@ -104,6 +104,29 @@ __device__ __forceinline__ uint64_t ef_rank(const EFDev& e, uint64_t x) {
   return i;
 }
 
+// Is x a code of the list?  The scan of rank(x) stops at the first code with
+// high part hx and low part at least x's: x is present exactly when that
+// position holds a one whose low part equals x's.
+__device__ __forceinline__ bool ef_contains(const EFDev& e, uint64_t x) {
+  if (e.m == 0) return false;
+  const uint64_t hx = x >> e.l;
+  if (hx >= e.n_zeros) return false;
+  uint64_t i = 0, p = 0;
+  if (hx > 0) {
+    const uint64_t p0 = ef_zero_pos(e, hx - 1);
+    i = p0 - (hx - 1);
+    p = p0 + 1;
+  }
+  const uint64_t xl = e.l ? (x & ((1ull << e.l) - 1)) : 0;
+  while (i < e.m && ((e.H[p >> 6] >> (p & 63)) & 1ull)) {
+    const uint64_t lw = ef_low(e, i);
+    if (lw >= xl) return lw == xl;
+    ++i;
+    ++p;
+  }
+  return false;
+}
+
 __device__ __forceinline__ int32_t ef_nbr(const EFDev& e, uint64_t idx) {
   return (int32_t)(ef_select(e, idx) & ((1ull << e.k) - 1));
 }
@@ -274,10 +297,25 @@ __global__ __launch_bounds__(256) void k_walk_lane_ef(WalkArgs a, EFDev e) {
 }
 
 // node2vec with 1/q != 1: one wavefront per walk, two passes over the biased
-// weights of N(v) (block sums, then a scan of the block holding the draw);
-// membership of a candidate x in N(t) is rank(phi(t, x)) landing on x.
+// weights of N(v) (block sums, then a scan of the block holding the draw).
+// Rows of at most kEfTile entries are decoded into LDS as they are streamed,
+// so the next step tests membership in N(t) by bisecting LDS; longer rows of
+// t are tested in the store itself.
+constexpr uint32_t kEfTile = 512;
+
+__device__ __forceinline__ bool lds_has(const int32_t* A, uint32_t n, int32_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (A[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < n && A[lo] == x;
+}
+
 template <bool WEIGHTED, typename RT>
-__device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, uint64_t w, int gl) {
+__device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, uint64_t w, int gl, int32_t* bufA,
+                                             int32_t* bufB) {
   constexpr int G = 64;
   const RT* __restrict__ R = (const RT*)a.g.R;
   const uint64_t P16 = a.P16, Q16 = a.Q16;
@@ -289,39 +327,50 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
     if (gl == 0) row[0] = start;
     len = 1;
     int32_t v = start, t = -1;
+    int32_t* cur = bufA;  // decoded N(t) when t_in_lds
+    int32_t* nxt = bufB;  // N(v) being decoded
+    bool t_in_lds = false;
+    uint32_t td = 0;
     uint64_t lo = ef_rank(e, (uint64_t)v << e.k);
     for (uint32_t s = 1; s < a.L; ++s) {
       const uint32_t d = (uint32_t)(ef_rank(e, ((uint64_t)v + 1) << e.k) - lo);
       if (d == 0) break;
       const uint64_t r = philox_draw(a.seed, s, wid);
+      const bool stage = a.second_order && d <= kEfTile;
       uint32_t jsel = d;
       if (!a.second_order || t < 0) {
         const uint64_t S = WEIGHTED ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
         if (S == 0) break;
         const uint64_t T = scale_draw(r, S);
         jsel = WEIGHTED ? upper_bound_gt(R + lo, d, T) : (uint32_t)T;
+        if (stage)
+          for (uint32_t j = (uint32_t)gl; j < d; j += G) nxt[j] = ef_nbr(e, lo + j);
       } else {
         const uint64_t tc0 = (uint64_t)t << e.k;
-        auto bias = [&](uint32_t j) -> uint64_t {
-          const int32_t x = ef_nbr(e, lo + j);
+        auto bias_of = [&](uint32_t j, int32_t x) -> uint64_t {
           const uint64_t wt = WEIGHTED ? weight_at(R, lo, j) : 1ull;
           if (x == t) return wt * P16;
-          const uint64_t c = tc0 | (uint64_t)(uint32_t)x;
-          const uint64_t rk = ef_rank(e, c);
-          return wt * ((rk < e.m && ef_select(e, rk) == c) ? (uint64_t)kC16 : Q16);
+          const bool common = t_in_lds ? lds_has(cur, td, x) : ef_contains(e, tc0 | (uint64_t)(uint32_t)x);
+          return wt * (common ? (uint64_t)kC16 : Q16);
         };
         const uint32_t nc = (d + G - 1) / G;
         const uint32_t bs = (nc + G - 1) / G;
         uint64_t acc = 0, blk = 0;
         for (uint32_t c = 0; c < nc; ++c) {
           const uint32_t j = c * G + (uint32_t)gl;
-          if (j < d) acc += bias(j);
+          if (j < d) {
+            const int32_t x = ef_nbr(e, lo + j);
+            if (stage) nxt[j] = x;
+            acc += bias_of(j, x);
+          }
           if ((c + 1) % bs == 0 || c + 1 == nc) {
             const uint64_t sb = grp_sum<G>(acc);
             if ((uint32_t)gl == c / bs) blk = sb;
             acc = 0;
           }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const uint64_t incl = grp_incl_scan<G>(blk, gl);
         const uint64_t total = grp_bcast<G>(incl, G - 1);
         if (total == 0) break;
@@ -332,7 +381,8 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
         const uint32_t cend = min((uint32_t)(kb + 1) * bs, nc);
         for (uint32_t c = (uint32_t)kb * bs; c < cend; ++c) {
           const uint32_t j = c * G + (uint32_t)gl;
-          const uint64_t b = j < d ? bias(j) : 0ull;
+          uint64_t b = 0;
+          if (j < d) b = bias_of(j, stage ? nxt[j] : ef_nbr(e, lo + j));
           const uint64_t inc = grp_incl_scan<G>(b, gl);
           const uint64_t m2 = grp_ballot<G>(base + inc > T, 0);
           if (m2) {
@@ -343,12 +393,24 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
         }
       }
       if (jsel >= d) break;  // unreachable: the draw lies below the total
-      const int32_t x = ef_nbr(e, lo + jsel);
+      // the staged row is read by other lanes of the wave from here on
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int32_t x = stage ? nxt[jsel] : ef_nbr(e, lo + jsel);
       if (gl == 0) row[s] = x;
       len = s + 1;
       t = v;
+      td = d;
+      t_in_lds = stage;
+      if (stage) {
+        int32_t* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+      }
       v = x;
       lo = ef_rank(e, (uint64_t)v << e.k);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   for (uint32_t s = len + (uint32_t)gl; s < a.L; s += G) row[s] = -1;
@@ -360,10 +422,12 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
 
 template <bool WEIGHTED, typename RT>
 __global__ __launch_bounds__(256) void k_walk_n2v_ef(WalkArgs a, EFDev e) {
+  __shared__ int32_t tiles[4][2][kEfTile];
   const int gl = threadIdx.x & 63;
+  const int wv = threadIdx.x / 64;
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
-  for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; w < a.nwalks; w += waves)
-    wave_walk_ef<WEIGHTED, RT>(a, e, w, gl);
+  for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / 64) + wv; w < a.nwalks; w += waves)
+    wave_walk_ef<WEIGHTED, RT>(a, e, w, gl, tiles[wv][0], tiles[wv][1]);
 }
 
 // Scale-free negatives: the node owning entry T of the edge list is the
