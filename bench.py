@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--runs", default="1,1;0.25,4", help="(p,q) pairs, ';'-separated")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--walk-len", type=int, default=100)
-    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served", "big", "corpus", "ef"],
+    ap.add_argument("--config", default="chung_lu_1m", choices=["chung_lu_1m", "batched", "served", "big", "corpus", "ef", "gather"],
                     help="chung_lu_1m: plain launches (default); batched: 64 graphs x 4096 requests, one "
                          "launch per request vs one persistent hipGraph launch; served: the same requests "
                          "under Poisson arrivals, server vs one launch per request")
@@ -220,6 +220,94 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}))
 
 
+# ---------------------------------------------------------------------------
+# Gather roofline: what random reads of a given granule achieve on this GPU
+# ---------------------------------------------------------------------------
+def _membench():
+    import ctypes
+    path = os.path.join(ROOT, "paper_2110_06196_amd", "libn2vmembench.so")
+    if not os.path.exists(path):
+        raise RuntimeError("libn2vmembench.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    u64, vp = ctypes.c_uint64, ctypes.c_void_p
+    lib.n2vm_gather.argtypes = [vp, u64, ctypes.c_uint32, u64, u64, vp, ctypes.c_int, vp]
+    lib.n2vm_stream.argtypes = [vp, u64, vp, ctypes.c_int, vp]
+    lib.n2vm_chase.argtypes = [vp, u64, ctypes.c_uint32, vp, vp]
+    for f in (lib.n2vm_gather, lib.n2vm_stream, lib.n2vm_chase):
+        f.restype = ctypes.c_int
+    return lib
+
+
+def _timed(torch, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def gather_bw(torch, nbytes: int, granule: int, useful_bytes: int = 4 << 30) -> float:
+    """Useful GB/s of random `granule`-byte reads over a buffer of nbytes (a power of two)."""
+    lib = _membench()
+    dev = torch.device("cuda:0")
+    buf = torch.zeros(nbytes // 4, dtype=torch.int32, device=dev)
+    sink = torch.zeros(1, dtype=torch.int64, device=dev)
+    grid = torch.cuda.get_device_properties(0).multi_processor_count * 32
+    n_items = useful_bytes // granule
+    st = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        rc = lib.n2vm_gather(buf.data_ptr(), nbytes // granule, granule, n_items, 12345, sink.data_ptr(), grid, st)
+        if rc != 0:
+            raise RuntimeError(f"n2vm_gather failed ({rc})")
+    t = _timed(torch, run)
+    del buf
+    return n_items * granule / t / 1e9
+
+
+def bench_gather(args):
+    """Random-gather bandwidth at 4/16/64/128 B over buffers resident in L2
+    (2 MiB), MALL (128 MiB) and HBM (16 GiB); streaming read of 16 GiB; and
+    single-lane pointer-chase latency over 2 MiB, 128 MiB and 1 GiB."""
+    import torch
+    dev = torch.device("cuda:0")
+    lib = _membench()
+    st = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for where, nbytes in (("L2", 2 << 20), ("MALL", 128 << 20), ("HBM", 16 << 30)):
+        for gran in (4, 16, 64, 128):
+            bw = gather_bw(torch, nbytes, gran)
+            rows.append({"buffer": where, "bytes": nbytes, "granule": gran, "useful_GBps": bw})
+            print(f"[bench] gather {where} {gran} B: {bw:.1f} GB/s", file=sys.stderr, flush=True)
+    buf = torch.zeros((16 << 30) // 4, dtype=torch.int32, device=dev)
+    sink = torch.zeros(1, dtype=torch.int64, device=dev)
+    grid = torch.cuda.get_device_properties(0).multi_processor_count * 32
+    t = _timed(torch, lambda: lib.n2vm_stream(buf.data_ptr(), 16 << 30, sink.data_ptr(), grid, st))
+    stream_bw = (16 << 30) / t / 1e9
+    del buf
+    lat = []
+    rng = np.random.default_rng(5)
+    for where, n in (("L2", (2 << 20) // 4), ("MALL", (128 << 20) // 4), ("HBM", (1 << 30) // 4)):
+        perm = rng.permutation(n).astype(np.uint32)
+        nxt = np.empty(n, dtype=np.uint32)
+        nxt[perm] = np.roll(perm, -1)  # one cycle through every slot
+        d_next = torch.from_numpy(nxt.view(np.int32)).to(dev)
+        hops = 100000
+        t = _timed(torch, lambda: lib.n2vm_chase(d_next.data_ptr(), hops, int(perm[0]), sink.data_ptr(), st), reps=2)
+        lat.append({"buffer": where, "bytes": n * 4, "ns_per_hop": t / hops * 1e9})
+        del d_next
+    out = {"metric": "memory-system probes (gather roofline)", "value": rows[-4]["useful_GBps"],
+           "unit": "GB/s (random 4 B over 16 GiB)", "n_gpus": 1, "steps": 3, "warmup": 1,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic", "config": {"workload": "random gathers / streaming read / pointer chase"},
+           "gather": rows, "stream_read_GBps": stream_bw, "chase": lat}
+    print(json.dumps(out), flush=True)
+
+
 def _clog2p1(x, torch):
     """ceil(log2(x + 1)) elementwise for int64 x >= 0."""
     return torch.ceil(torch.log2((x + 1).to(torch.float64))).to(torch.int64)
@@ -314,6 +402,9 @@ def main():
     if args.config == "ef":
         bench_ef(args)
         return
+    if args.config == "gather":
+        bench_gather(args)
+        return
     import torch
     import paper_2110_06196_amd as n2v
 
@@ -376,6 +467,12 @@ def main():
     dom = max(kernels, key=lambda k: k["mean_ms"])
     traffic = traffic_from_profiles(KERNEL_OF_PATH[dom["path"]])
     value = total_steps * args.steps / t_total
+    # measured gather roofline at the size of what the walks read (offsets,
+    # destinations, weights, row prefix), rounded up to a power of two
+    ws = O.nbytes + D.nbytes + W.nbytes + D.size * max(1, info["prefix_bytes"])
+    ws2 = 1 << int(np.ceil(np.log2(ws)))
+    g4, g64 = gather_bw(torch, ws2, 4), gather_bw(torch, ws2, 64)
+    print(f"[bench] gather roofline over {ws2} B: 4 B {g4:.0f} GB/s, 64 B {g64:.0f} GB/s", file=sys.stderr, flush=True)
 
     # CPU baseline: the oracle on an evenly spaced sample of the same walks.
     cpu = None
@@ -436,6 +533,13 @@ def main():
             "frac": dom["alg_GBps"] / HBM_PEAK_GBS,
             "traffic": traffic,
             "kernel": f"node2vec p={dom['p']:g} q={dom['q']:g} ({dom['path']})",
+            "measured_hbm_GBps": (traffic / (dom["mean_ms"] / 1e3) / 1e9) if traffic else None,
+        },
+        "gather_roofline": {
+            "buffer_bytes": ws2, "random_4B_GBps": g4, "random_64B_GBps": g64,
+            "kernel_fetch_GBps": (traffic / (dom["mean_ms"] / 1e3) / 1e9) if traffic else None,
+            "note": "useful GB/s of random 4 B / 64 B reads over a buffer the size of the graph arrays, measured "
+                    "in this run, beside the dominant kernel's measured HBM traffic rate (committed PMC profile)",
         },
         "cpu_baseline": cpu,
         "kernels": kernels,

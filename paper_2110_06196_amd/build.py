@@ -19,6 +19,10 @@ LIB = os.path.join(PKG, "libn2vwalk.so")
 
 SOURCES = ["n2v_api.cpp", "n2v_serve.cpp", "n2v_prep.hip", "n2v_walk.hip", "n2v_corpus.hip", "n2v_ef.hip"]
 
+# memory-system probes for the benchmark's gather roofline (not the walk library)
+MEMBENCH_SOURCES = ["n2v_membench.hip"]
+MEMBENCH_LIB = os.path.join(PKG, "libn2vmembench.so")
+
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -48,18 +52,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + f".tmp{os.getpid()}"
+def _link(objs, lib):
+    tmp = lib + f".tmp{os.getpid()}"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr[-8000:]}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Build the walk library and the memory-probe library used by the benchmark."""
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        objs = list(ex.map(_compile, SOURCES + MEMBENCH_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], MEMBENCH_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {MEMBENCH_LIB}")
     return LIB
 
 
