@@ -173,6 +173,51 @@ __device__ __forceinline__ uint32_t upper_bound_gt(const RT* R, uint32_t d, uint
   return lo;
 }
 
+// First j in [0, d) with f(j) > T, for f non-decreasing with f(d - 1) = S > T
+// (a row prefix, or one scaled and shifted at a single position), found with
+// fewer dependent loads when f grows roughly linearly, as row prefixes of
+// weights do: up to three rounds probe a window of 33 entries around the point
+// where the line through the bracket's end values crosses T (both ends of the
+// window in flight together), then a bisection finishes inside the bracket.
+// Invariant: the answer lies in [lo, hi], f(lo - 1) <= T (flo; 0 before the
+// row), f(hi) > T (fhi).
+template <typename F>
+__device__ __forceinline__ uint32_t first_above_interp(uint32_t d, uint64_t T, uint64_t S, F f) {
+  uint32_t lo = 0, hi = d - 1;
+  uint64_t flo = 0, fhi = S;
+  for (int round = 0; round < 3 && hi - lo > 32; ++round) {
+    const double frac = (double)(T - flo) / (double)(fhi - flo);
+    uint32_t g = lo + (uint32_t)(frac * (double)(hi - lo));
+    if (g > hi - 1) g = hi - 1;
+    const uint32_t a = g > lo + 16 ? g - 16 : lo;
+    const uint32_t b = g + 16 < hi - 1 ? g + 16 : hi - 1;
+    const uint64_t fa = f(a), fb = f(b);
+    if (fa > T) {
+      hi = a;
+      fhi = fa;
+    } else if (fb > T) {
+      lo = a + 1;
+      flo = fa;
+      hi = b;
+      fhi = fb;
+    } else {
+      lo = b + 1;
+      flo = fb;
+    }
+  }
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (f(mid) > T) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+template <typename RT>
+__device__ __forceinline__ uint32_t upper_bound_interp(const RT* R, uint32_t d, uint64_t T, uint64_t S) {
+  return first_above_interp(d, T, S, [&](uint32_t j) -> uint64_t { return (uint64_t)R[j]; });
+}
+
 // First index j in [0, d) with D[j] >= x; d if none.
 __device__ __forceinline__ uint32_t lower_bound_i32(const int32_t* D, uint32_t d, int32_t x) {
   uint32_t lo = 0, hi = d;

@@ -77,7 +77,7 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
         } else if (MODE == kFoW || (MODE == kRetW && t < 0)) {
           const uint64_t total = (uint64_t)R[lo + d - 1];
           if (total == 0) break;  // every candidate has weight zero
-          j = upper_bound_gt(R + lo, d, scale_draw(r, total));
+          j = upper_bound_interp(R + lo, d, scale_draw(r, total), total);
         } else {
           const uint32_t pt = lower_bound_i32(D + lo, d, t);
           const bool has_t = pt < d && D[lo + pt] == t;

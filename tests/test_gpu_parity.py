@@ -171,3 +171,47 @@ def test_errors():
     with pytest.raises(n2v.N2VError) as e:
         run(g, [0], 1, 5, FO)
     assert e.value.code == n2v.N2V_ERR_BAD_HANDLE
+
+
+def _skewed_graph(kinds, seed):
+    rng = np.random.default_rng(seed)
+    n = 6000
+    src, dst, wts = [], [], []
+    for h, kind in enumerate(kinds):
+        nb = np.arange(10, 10 + 4000)
+        w = np.ones(nb.size, dtype=np.int64)
+        if kind == "front":
+            w[0] = 2**30
+        elif kind == "middle":
+            w[nb.size // 2] = 2**30
+        elif kind == "back":
+            w[-1] = 2**30
+        elif kind == "geometric":
+            w = np.minimum(2 ** (np.arange(nb.size) // 150), 2**30).astype(np.int64)
+        else:
+            w = np.where(rng.random(nb.size) < 0.9, 0, rng.integers(1, 100, nb.size))
+            w[-1] = 5
+        src += [h] * nb.size
+        dst += list(nb)
+        wts += list(w)
+    # every hub's neighbours point back to every hub, so walks keep returning
+    for x in range(10, 4010):
+        for h in range(len(kinds)):
+            src.append(x)
+            dst.append(h)
+            wts.append(int(rng.integers(1, 50)))
+    return synth.csr_from_edges(n, np.array(src), np.array(dst), np.array(wts, dtype=np.uint32)), len(kinds)
+
+
+@pytest.mark.parametrize("kinds", [("front", "middle", "back", "zeros"), ("geometric", "front")])
+def test_first_order_skewed_prefixes(kinds):
+    # Row prefixes far from linear drive the interpolated prefix search through
+    # every bracket case: one dominant weight at the start, middle or end of a
+    # long row, geometric weights (64-bit prefix), runs of zero weights.
+    (O, D, W), nh = _skewed_graph(kinds, 31)
+    g, keep = upload(O, D, W)
+    starts = np.concatenate([np.arange(nh), np.arange(10, 4010, 7)])
+    Y, lens = run(g, starts, 20, 30, FO, seed=4)
+    Yo, lo = oracle.walks(O, D, W, starts, 20, 30, FO, seed=4)
+    assert np.array_equal(Y, Yo) and np.array_equal(lens, lo)
+    n2v.n2v_graph_release(g)
