@@ -127,6 +127,31 @@ __device__ __forceinline__ bool ef_contains(const EFDev& e, uint64_t x) {
   return false;
 }
 
+// rank(x), and whether x is present (the scan's stopping code equals x).
+__device__ __forceinline__ uint64_t ef_rank_has(const EFDev& e, uint64_t x, bool* has) {
+  *has = false;
+  if (e.m == 0) return 0;
+  const uint64_t hx = x >> e.l;
+  if (hx >= e.n_zeros) return e.m;
+  uint64_t i = 0, p = 0;
+  if (hx > 0) {
+    const uint64_t p0 = ef_zero_pos(e, hx - 1);
+    i = p0 - (hx - 1);
+    p = p0 + 1;
+  }
+  const uint64_t xl = e.l ? (x & ((1ull << e.l) - 1)) : 0;
+  while (i < e.m && ((e.H[p >> 6] >> (p & 63)) & 1ull)) {
+    const uint64_t lw = ef_low(e, i);
+    if (lw >= xl) {
+      *has = lw == xl;
+      return i;
+    }
+    ++i;
+    ++p;
+  }
+  return i;
+}
+
 __device__ __forceinline__ int32_t ef_nbr(const EFDev& e, uint64_t idx) {
   return (int32_t)(ef_select(e, idx) & ((1ull << e.k) - 1));
 }
@@ -302,6 +327,7 @@ __global__ __launch_bounds__(256) void k_walk_lane_ef(WalkArgs a, EFDev e) {
 // so the next step tests membership in N(t) by bisecting LDS; longer rows of
 // t are tested in the store itself.
 constexpr uint32_t kEfTile = 512;
+constexpr uint32_t kEfList = kEfTile;  // common-neighbour list of the probe route (in the idle tile)
 
 __device__ __forceinline__ bool lds_has(const int32_t* A, uint32_t n, int32_t x) {
   uint32_t lo = 0, hi = n;
@@ -331,7 +357,10 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
     int32_t* nxt = bufB;  // N(v) being decoded
     bool t_in_lds = false;
     uint32_t td = 0;
+    uint64_t tlo = 0;
     uint64_t lo = ef_rank(e, (uint64_t)v << e.k);
+    const uint64_t lt_mask = gl == 0 ? 0ull : (~0ull >> (64 - gl));
+    auto Rv = [&](uint32_t j) -> uint64_t { return WEIGHTED ? (uint64_t)R[lo + j] : (uint64_t)j + 1ull; };
     for (uint32_t s = 1; s < a.L; ++s) {
       const uint32_t d = (uint32_t)(ef_rank(e, ((uint64_t)v + 1) << e.k) - lo);
       if (d == 0) break;
@@ -346,6 +375,95 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
         if (stage)
           for (uint32_t j = (uint32_t)gl; j < d; j += G) nxt[j] = ef_nbr(e, lo + j);
       } else {
+        bool done = false;
+        if (d > kEfTile && ((uint64_t)td + 1) * 4 < d) {
+          // Probe route: rank every key of N(t) (and t) into N(v).  Hits are
+          // the common neighbours' positions, in increasing order; the draw
+          // is located through them and a bisection of the row prefix between
+          // two of them, B_j = Q16 R_j + (C16 - Q16) sum_{common c <= j} w_c
+          // + (P16 - Q16) w_t [j >= pt] (mod 2^64, exact).
+          // rows longer than the tile are not staged, so nxt holds the list
+          uint32_t* const lpos = reinterpret_cast<uint32_t*>(nxt);
+          const uint64_t vc0 = (uint64_t)v << e.k;
+          uint32_t cnt = 0, pt = 0;
+          bool has_t = false;
+          uint64_t cw = 0;
+          for (uint32_t c = 0; c < td + 1; c += G) {
+            const uint32_t k = c + (uint32_t)gl;
+            const bool tkey = k == td;
+            bool hit = false;
+            uint32_t pos = 0;
+            int32_t y = t;
+            if (k < td) y = t_in_lds ? cur[k] : ef_nbr(e, tlo + k);
+            if (k <= td) pos = (uint32_t)(ef_rank_has(e, vc0 | (uint64_t)(uint32_t)y, &hit) - lo);
+            const uint64_t mt = grp_ballot<G>(hit && tkey, 0);
+            if (mt) {
+              has_t = true;
+              pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
+            }
+            // a self-loop at t puts t in N(t): that candidate is a return, not common
+            const bool common = hit && !tkey && y != t;
+            const uint64_t m = grp_ballot<G>(common, 0);
+            if (common) {
+              cw += WEIGHTED ? weight_at(R, lo, pos) : 1ull;
+              const uint32_t idx = cnt + (uint32_t)__popcll(m & lt_mask);
+              if (idx < kEfList) lpos[idx] = pos;
+            }
+            cnt += (uint32_t)__popcll(m);
+          }
+          if (cnt <= kEfList) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint64_t cdel = (uint64_t)kC16 - Q16, rdel = P16 - Q16;
+            const uint64_t CW = grp_sum<G>(cw);
+            const uint64_t wt = has_t ? (WEIGHTED ? weight_at(R, lo, pt) : 1ull) : 0ull;
+            const uint64_t retw = rdel * wt;
+            const uint64_t S = WEIGHTED ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
+            const uint64_t total = Q16 * S + cdel * CW + retw;
+            if (total == 0) break;
+            const uint64_t T = scale_draw(r, total);
+            // first listed position whose B exceeds T: the segment before it
+            // holds no common neighbour
+            uint64_t E = 0, Eseg = CW;
+            uint32_t seg_lo = 0, seg_end = d, lastpos = 0;
+            bool found = false, any = false;
+            for (uint32_t c = 0; c < cnt; c += G) {
+              const uint32_t k = c + (uint32_t)gl;
+              const bool act = k < cnt;
+              const uint32_t p = act ? lpos[k] : 0u;
+              const uint64_t wk = act ? (WEIGHTED ? weight_at(R, lo, p) : 1ull) : 0ull;
+              const uint64_t inc = grp_incl_scan<G>(wk, gl);
+              const uint64_t Ek = E + inc;
+              const uint64_t Bk = Q16 * Rv(p) + cdel * Ek + ((has_t && p >= pt) ? retw : 0ull);
+              const uint64_t mb = grp_ballot<G>(act && Bk > T, 0);
+              if (mb) {
+                const int f = __ffsll((unsigned long long)mb) - 1;
+                Eseg = grp_bcast<G>(Ek - wk, f);
+                seg_end = (uint32_t)grp_bcast_i32<G>((int32_t)p, f);
+                const uint32_t pprev = (uint32_t)grp_bcast_i32<G>((int32_t)p, f > 0 ? f - 1 : 0);
+                seg_lo = f > 0 ? pprev + 1 : (any ? lastpos + 1 : 0u);
+                found = true;
+                break;
+              }
+              const uint32_t nact = min((uint32_t)G, cnt - c);
+              lastpos = (uint32_t)grp_bcast_i32<G>((int32_t)p, (int)nact - 1);
+              any = true;
+              E += grp_bcast<G>(inc, G - 1);
+            }
+            if (!found) seg_lo = any ? lastpos + 1 : 0u;
+            // first j in [seg_lo, seg_end) with B_j > T (common weight Eseg
+            // there); none: the listed position seg_end itself
+            uint32_t jl = seg_lo, jh = seg_end;
+            while (jl < jh) {
+              const uint32_t mid = jl + ((jh - jl) >> 1);
+              if (Q16 * Rv(mid) + cdel * Eseg + ((has_t && mid >= pt) ? retw : 0ull) > T) jh = mid;
+              else jl = mid + 1;
+            }
+            jsel = jl;
+            done = true;
+          }
+        }
+        if (!done) {
         const uint64_t tc0 = (uint64_t)t << e.k;
         auto bias_of = [&](uint32_t j, int32_t x) -> uint64_t {
           const uint64_t wt = WEIGHTED ? weight_at(R, lo, j) : 1ull;
@@ -391,6 +509,7 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
           }
           base += grp_bcast<G>(inc, G - 1);
         }
+        }
       }
       if (jsel >= d) break;  // unreachable: the draw lies below the total
       // the staged row is read by other lanes of the wave from here on
@@ -401,6 +520,7 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
       len = s + 1;
       t = v;
       td = d;
+      tlo = lo;
       t_in_lds = stage;
       if (stage) {
         int32_t* tmp = cur;
