@@ -78,3 +78,46 @@ def test_power_law_hubs_sampled():
         steps = _check(g, host, n, starts, 40, kind, p, q, 42, rows)
         assert steps > 0
     n2v.n2v_graph_release(g)
+
+
+def test_chung_lu_1m_full_size_sampled():
+    # The 1M-node workload exactly as the benchmark runs it: every node starts
+    # 10 walks of 100 slots, (p, q) = (1, 1) and (0.25, 4), seed 42, plain
+    # calls with the automatic launch shape; 2000 rows per run against the oracle.
+    O, D, W = synth.chung_lu_1m()
+    n = len(O) - 1
+    dev = torch.device("cuda")
+    Ot = torch.from_numpy(O.view(np.int64)).to(dev)
+    Dt = torch.from_numpy(D).to(dev)
+    Wt = torch.from_numpy(W.view(np.int32)).to(dev)
+    g = n2v.n2v_graph_upload(Ot, Dt, Wt)
+    S = torch.arange(n, dtype=torch.int32, device=dev)
+    Y = torch.empty((10 * n, 100), dtype=torch.int32, device=dev)
+    lens = torch.empty(10 * n, dtype=torch.int32, device=dev)
+    rows = np.linspace(0, 10 * n - 1, 2000).astype(np.int64)
+    idx = torch.from_numpy(rows).to(dev)
+    for p, q in [(1.0, 1.0), (0.25, 4.0)]:
+        n2v.n2v_walks_node2vec(g, S, 10, 100, p, q, 42, 0, Y, lens)
+        torch.cuda.synchronize()
+        Yo, lo = oracle.walks_threaded(O, D, W, np.arange(n, dtype=np.int32), 10, 100, oracle.NODE2VEC, p, q, 42, 0,
+                                       rows, 16)
+        assert np.array_equal(Y.index_select(0, idx).cpu().numpy(), Yo), (p, q)
+        assert np.array_equal(lens.index_select(0, idx).cpu().numpy(), lo), (p, q)
+    n2v.n2v_graph_release(g)
+
+
+def test_chung_lu_20m_full_size_sampled():
+    # The 20M-node hub workload at full size (1e9 undirected edge samples,
+    # 1.9e9 entries, max degree about 1.25e6), generated on the GPU: one walk
+    # of 80 slots per node, first order and node2vec (1, 2); 150 rows each.
+    n, ne = 20_000_000, 1_000_000_000
+    O, D, W = synth.chung_lu_device(n, ne, 2.2, 2.0 * ne / n, 2.0e6, (1, 255), seed=3)
+    g = n2v.n2v_graph_upload(O, D, W)
+    info = n2v.n2v_graph_info(g)
+    assert info["n_entries"] > 1.8e9 and info["max_degree"] > 1e6
+    host = _host(O, D, W)
+    starts = np.arange(n, dtype=np.int32)
+    rows = np.linspace(0, n - 1, 150).astype(np.int64)
+    for kind, p, q in [(n2v.N2V_FIRST_ORDER, 1.0, 1.0), (n2v.N2V_NODE2VEC, 1.0, 2.0)]:
+        _check(g, host, n, starts, 80, kind, p, q, 42, rows)
+    n2v.n2v_graph_release(g)
