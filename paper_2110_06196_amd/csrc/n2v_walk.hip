@@ -251,6 +251,13 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         auto Rv = [&](uint32_t j) -> uint64_t {
           return WEIGHTED ? (uint64_t)R[lo + j] : (uint64_t)j + 1ull;
         };
+        // weight of candidate j as a difference of the row prefix: the walk
+        // reads one array (R) instead of two (R and W)
+        auto Wv = [&](uint32_t j) -> uint64_t {
+          if (!WEIGHTED) return 1ull;
+          const uint64_t hi = (uint64_t)R[lo + j];
+          return j ? hi - (uint64_t)R[lo + j - 1] : hi;
+        };
         const uint64_t S = Rv(d - 1);  // row weight sum
         uint32_t jsel = 0xFFFFFFFFu;
         bool staged = false;
@@ -427,7 +434,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
               if (m == 0) return;
               if (hit) {
                 const uint32_t idx = stored + (uint32_t)__popcll(m & lt_mask);
-                const uint32_t wv = WEIGHTED ? W[lo + pos] : 1u;
+                const uint32_t wv = (uint32_t)Wv(pos);
                 if (first) acc += wv;
                 if (idx < (uint32_t)cap) {
                   lpos[idx] = pos;
@@ -563,7 +570,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             gen(0);  // first pass: every hit counted, first page stored
             first = false;
             const uint64_t CW = grp_sum<G>(acc);
-            const uint64_t wt = has_t ? (WEIGHTED ? (uint64_t)W[lo + pt] : 1ull) : 0ull;
+            const uint64_t wt = has_t ? Wv(pt) : 0ull;
             const uint64_t retw = rdel * wt;
             const uint64_t total = Q16 * S + cdel * CW + retw;
             if (total == 0) break;
