@@ -339,12 +339,22 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             return st + (uint32_t)scale_draw(rr, ln);
           };
           const bool second = a.second_order && t >= 0;
+          // a long N(t) outside LDS: bisections start from its splitters
+          const bool split_t = second && !t_in_lds && td >= 4u * G;
+          if (split_t) load_splitters<G>(D + tlo, td, win, gl);
           auto weight = [&](uint32_t p) -> uint64_t {
             const int32_t x = D[lo + p];
             const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + p] : 1ull;
             if (!second) return wt;
             if (x == t) return wt * P16;
-            return wt * (member(x) ? (uint64_t)kC16 : Q16);
+            bool common;
+            if (split_t) {
+              const uint32_t q = lower_bound_split<G>(D + tlo, td, win, x);
+              common = q < td && D[tlo + q] == x;
+            } else {
+              common = member(x);
+            }
+            return wt * (common ? (uint64_t)kC16 : Q16);
           };
           const uint32_t nc = (k + G - 1) / G;
           const uint32_t bs = (nc + G - 1) / G;
