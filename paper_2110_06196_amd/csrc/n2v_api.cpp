@@ -243,7 +243,8 @@ GraphRec* new_record(uint64_t n_nodes, uint64_t n_entries, const uint64_t h[4], 
 }
 
 // The per-row inclusive weight prefix (owned), 32-bit when every row sum fits.
-int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weights, hipStream_t st) {
+int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weights, hipStream_t st,
+                 bool node_records) {
   if (!d_weights || gr->n_entries == 0) return N2V_OK;
   const uint32_t rb = gr->max_row_wsum <= 0xFFFFFFFFull ? 4u : 8u;
   void* R = nullptr;
@@ -260,6 +261,20 @@ int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weig
   gr->dev.R = R;
   gr->dev.r_bytes = rb;
   gr->owned_bytes += gr->n_entries * rb;
+  if (rb == 4 && node_records) {
+    uint4* NR = nullptr;
+    e = hipMalloc(&NR, (size_t)gr->dev.n * sizeof(uint4));
+    if (e != hipSuccess)
+      return fail(N2V_ERR_NOMEM, "hipMalloc node records: %s", hipGetErrorString(e));
+    e = launch_node_records(d_offsets, gr->dev.n, (const uint32_t*)R, NR, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      hipFree(NR);
+      return hip_fail(e, "node records");
+    }
+    gr->dev.NR = NR;
+    gr->owned_bytes += (uint64_t)gr->dev.n * sizeof(uint4);
+  }
   return N2V_OK;
 }
 
@@ -272,6 +287,7 @@ n2v_graph register_graph(GraphRec* gr) {
 
 void free_record(GraphRec* gr) {
   if (gr->dev.R) hipFree(const_cast<void*>(gr->dev.R));
+  if (gr->dev.NR) hipFree(const_cast<uint4*>(gr->dev.NR));
   if (gr->neg_guide) hipFree(gr->neg_guide);
   if (gr->ef_mem) hipFree(gr->ef_mem);
   delete gr;
@@ -301,7 +317,7 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
   gr->dev.O = d_offsets;
   gr->dev.D = d_dst;
   gr->dev.W = d_weights;
-  rc = build_prefix(gr, d_offsets, d_weights, st);
+  rc = build_prefix(gr, d_offsets, d_weights, st, true);
   if (rc != N2V_OK) {
     free_record(gr);
     return rc;
@@ -355,7 +371,7 @@ int n2v_graph_upload_ef(const uint64_t* d_offsets, uint64_t n_nodes, const int32
     free_record(gr);
     return hip_fail(e, "Elias-Fano build");
   }
-  rc = build_prefix(gr, d_offsets, d_weights, st);
+  rc = build_prefix(gr, d_offsets, d_weights, st, false);
   if (rc != N2V_OK) {
     free_record(gr);
     return rc;

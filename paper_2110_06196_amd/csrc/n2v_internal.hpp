@@ -16,6 +16,10 @@ struct GraphDev {
   uint32_t r_bytes = 0;         // 0 (unweighted), 4 or 8
   int64_t n = 0;
   uint64_t m = 0;
+  // Weighted graphs with 32-bit row sums: per node {O[v] lo, O[v] hi, d_v,
+  // S_v} in one 16-byte record, so a step reads its row's offset, degree and
+  // weight sum with one load.  Null otherwise.
+  const uint4* NR = nullptr;
 };
 
 // Which kernel family serves a request.
@@ -88,6 +92,7 @@ hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint
 // [3] sum of degree^2 (device uint64[4], zeroed by the caller).
 hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
                                  const uint32_t* W, uint64_t* stats, hipStream_t st);
+hipError_t launch_node_records(const uint64_t* O, int64_t n, const uint32_t* R, uint4* NR, hipStream_t st);
 hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,
                              uint32_t r_bytes, hipStream_t st);
 

@@ -87,6 +87,15 @@ __global__ __launch_bounds__(256) void k_row_prefix(const uint64_t* __restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_node_records(const uint64_t* __restrict__ O, int64_t n,
+                                                      const uint32_t* __restrict__ R, uint4* __restrict__ NR) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = O[v];
+    const uint64_t d = O[v + 1] - lo;
+    NR[v] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)d, d ? R[lo + d - 1] : 0u);
+  }
+}
+
 int prep_blocks(int64_t n) {
   int64_t waves = n;  // one wave per row
   int64_t blocks = (waves + 3) / 4;
@@ -101,6 +110,11 @@ hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D,
                                  const uint32_t* W, uint64_t* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_validate_stats, dim3(prep_blocks(n)), dim3(256), 0, st, O, n, D, m, W,
                      (unsigned long long*)stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_records(const uint64_t* O, int64_t n, const uint32_t* R, uint4* NR, hipStream_t st) {
+  hipLaunchKernelGGL(k_node_records, dim3(prep_blocks(n)), dim3(256), 0, st, O, n, R, NR);
   return hipGetLastError();
 }
 

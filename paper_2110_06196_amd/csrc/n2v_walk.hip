@@ -67,15 +67,26 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
       len = 1;
       int32_t v = start, t = -1;
       for (uint32_t s = 1; s < a.L; ++s) {
-        const uint64_t lo = O[v];
-        const uint32_t d = (uint32_t)(O[v + 1] - lo);
+        uint64_t lo;
+        uint32_t d;
+        uint64_t rowsum = 0;  // S_v from the node record when there is one
+        constexpr bool kRec = (MODE == kFoW || MODE == kRetW) && sizeof(RT) == 4;
+        if (kRec && a.g.NR) {
+          const uint4 rec = a.g.NR[v];
+          lo = (uint64_t)rec.x | ((uint64_t)rec.y << 32);
+          d = rec.z;
+          rowsum = rec.w;
+        } else {
+          lo = O[v];
+          d = (uint32_t)(O[v + 1] - lo);
+        }
         if (d == 0) break;  // dead end
         const uint64_t r = philox_draw(a.seed, s, wid);
         uint32_t j;
         if (MODE == kFoUnw || (MODE == kRetUnw && t < 0)) {
           j = (uint32_t)scale_draw(r, d);
         } else if (MODE == kFoW || (MODE == kRetW && t < 0)) {
-          const uint64_t total = (uint64_t)R[lo + d - 1];
+          const uint64_t total = (kRec && a.g.NR) ? rowsum : (uint64_t)R[lo + d - 1];
           if (total == 0) break;  // every candidate has weight zero
           j = upper_bound_interp(R + lo, d, scale_draw(r, total), total);
         } else {
@@ -83,7 +94,8 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
           const bool has_t = pt < d && D[lo + pt] == t;
           uint64_t wt = 0;
           if (has_t) wt = (MODE == kRetW) ? (uint64_t)W[lo + pt] : 1ull;
-          const uint64_t S = (MODE == kRetW) ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
+          const uint64_t S =
+              (MODE == kRetW) ? ((kRec && a.g.NR) ? rowsum : (uint64_t)R[lo + d - 1]) : (uint64_t)d;
           const uint64_t corr = ((uint64_t)a.P16 - (uint64_t)kC16) * wt;  // mod 2^64
           const uint64_t total = (uint64_t)kC16 * S + corr;
           if (total == 0) break;
