@@ -55,7 +55,6 @@ template <int MODE, typename RT>
 __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
-  const uint32_t* __restrict__ W = a.g.W;
   const RT* __restrict__ R = (const RT*)a.g.R;
   {
     int32_t* __restrict__ row = a.Y + w * a.L;
@@ -93,7 +92,7 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
           const uint32_t pt = lower_bound_i32(D + lo, d, t);
           const bool has_t = pt < d && D[lo + pt] == t;
           uint64_t wt = 0;
-          if (has_t) wt = (MODE == kRetW) ? (uint64_t)W[lo + pt] : 1ull;
+          if (has_t) wt = (MODE == kRetW) ? (uint64_t)a.g.W[lo + pt] : 1ull;
           const uint64_t S =
               (MODE == kRetW) ? ((kRec && a.g.NR) ? rowsum : (uint64_t)R[lo + d - 1]) : (uint64_t)d;
           const uint64_t corr = ((uint64_t)a.P16 - (uint64_t)kC16) * wt;  // mod 2^64
@@ -232,7 +231,6 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   int32_t* const win = (int32_t*)(lw + cap);
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
-  const uint32_t* __restrict__ W = a.g.W;
   const RT* __restrict__ R = (const RT*)a.g.R;
   const uint64_t lt_mask = (gl == 0) ? 0ull : ((~0ull) >> (64 - gl));  // group lanes below gl
   const uint64_t P16 = a.P16, Q16 = a.Q16;
@@ -295,7 +293,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             if (j < d) {
               const int32_t x = D[lo + j];
               if (stg) nxt[j] = x;
-              const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + j] : 1ull;
+              const uint64_t wt = Wv(j);
               acc += wt * alpha(x);
             }
             if ((c + 1) % bs == 0 || c + 1 == nc) {
@@ -321,7 +319,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             uint64_t b = 0;
             if (j < d) {
               const int32_t x = stg ? nxt[j] : D[lo + j];
-              const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + j] : 1ull;
+              const uint64_t wt = Wv(j);
               b = wt * alpha(x);
             }
             const uint64_t inc = grp_incl_scan<G>(b, gl);
@@ -356,7 +354,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           if (split_t) load_splitters<G>(D + tlo, td, win, gl);
           auto weight = [&](uint32_t p) -> uint64_t {
             const int32_t x = D[lo + p];
-            const uint64_t wt = WEIGHTED ? (uint64_t)W[lo + p] : 1ull;
+            const uint64_t wt = Wv(p);
             if (!second) return wt;
             if (x == t) return wt * P16;
             bool common;
