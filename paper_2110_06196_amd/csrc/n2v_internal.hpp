@@ -60,6 +60,7 @@ struct LaunchCfg {
   int list_cap = 256;         // common-neighbour list entries per walker in LDS
   int mode = 0;               // 0 auto, 1 two-pass streaming, 2 probe N(t), 3 stream N(v)
   int grid_blocks = 0;        // 0 = derive from occupancy
+  int full = 1;               // queue kernel with approximated steps and the two-pass route (0: exact routes only)
 };
 
 // LDS words per walker group of g lanes: two staging tiles of the previous

@@ -65,6 +65,14 @@ int prepare_all(const n2v_request_desc_t* reqs, uint32_t n, std::vector<Prepared
   return N2V_OK;
 }
 
+// Whether any request takes approximated steps (the queue kernel then needs
+// its full instantiation).
+bool needs_full(const std::vector<Prepared>& reqs) {
+  for (const Prepared& r : reqs)
+    if (r.args.k_approx != 0) return true;
+  return false;
+}
+
 // Split every request into chunks of roughly `target` units (lane-path
 // chunks are whole multiples of 64 rows, so every group shape fills its
 // lanes) and order them longest-estimated-first.
@@ -212,6 +220,7 @@ int autotune(BatchPlan* p) {
     c.lanes_per_walker = sh[0];
     c.lds_tile = sh[1];
     c.list_cap = sh[2];
+    c.full = needs_full(p->reqs) ? 1 : 0;
     if (block_lds_bytes(c.lanes_per_walker, c.lds_tile, c.list_cap) > p->di.lds_per_block_max) continue;
     float ms_min = 1e30f;
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
@@ -415,9 +424,13 @@ int launch_quantum(Server* s, Quantum* q, const std::vector<WalkArgs>& reqs, con
   std::memcpy(q->h_stage, reqs.data(), rb);
   std::memcpy(q->h_stage + off_c, chunks.data(), cb);
   hipError_t e = hipMemcpyAsync(q->block, q->h_stage, off_h, hipMemcpyHostToDevice, s->st);
+  LaunchCfg cfg = s->cfg;
+  cfg.full = 0;
+  for (const WalkArgs& r : reqs)
+    if (r.k_approx != 0) cfg.full = 1;
   if (e == hipSuccess)
     e = launch_queue((WalkArgs*)q->block, (QueueChunk*)((uint8_t*)q->block + off_c), (uint32_t)chunks.size(),
-                     (uint32_t*)((uint8_t*)q->block + off_h), s->cfg, s->di, s->st);
+                     (uint32_t*)((uint8_t*)q->block + off_h), cfg, s->di, s->st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(q->h_steps, s->d_steps, sizeof(uint64_t) * s->max_slots, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipEventRecord(q->done, s->st);
@@ -544,6 +557,7 @@ int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip
   if (rc != N2V_OK) return rc;
   LaunchCfg cfg = batch_default_cfg(di);
   apply_tuning_override(&cfg, di);
+  cfg.full = needs_full(pr) ? 1 : 0;
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = launch_queue(dr, dc, (uint32_t)chunks.size(), dh, cfg, di, st);
   hipEvent_t ev;
@@ -580,6 +594,7 @@ int n2v_batch_create(const n2v_request_desc_t* reqs, uint32_t n_reqs, uint32_t f
     return fail(N2V_ERR_INVALID_ARG, "too many chunks");
   }
   p->cfg = batch_default_cfg(p->di);
+  p->cfg.full = needs_full(p->reqs) ? 1 : 0;
   rc = upload_tables(p->reqs, p->chunks, &p->block, &p->d_reqs, &p->d_chunks, &p->d_head);
   if (rc == N2V_OK && (flags & N2V_BATCH_AUTOTUNE)) rc = autotune(p);
   apply_tuning_override(&p->cfg, p->di);  // an explicit n2v_set_tuning wins

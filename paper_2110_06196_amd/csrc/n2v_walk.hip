@@ -710,7 +710,7 @@ __device__ __forceinline__ void lane_dispatch(const WalkArgs& a, uint64_t w) {
   }
 }
 
-template <int G>
+template <int G, bool FULL>
 __global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkArgs* __restrict__ reqs,
                                                     const QueueChunk* __restrict__ chunks, uint32_t nchunks,
                                                     uint32_t* __restrict__ head, int tile, int cap,
@@ -729,11 +729,11 @@ __global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkA
     if (a.path != (uint32_t)Path::kGeneric) {
       for (uint64_t w = ch.w0 + (uint64_t)gl; w < ch.w1; w += G) lane_dispatch<G>(a, w);
     } else if (a.g.W == nullptr) {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, false, uint32_t, true>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, false, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
     } else if (a.g.r_bytes == 8) {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint64_t, true>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint64_t, FULL>(a, w, mem, tile, cap, mode_knob);
     } else {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint32_t, true>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
     }
   }
 }
@@ -795,10 +795,14 @@ hipError_t go_n2v_g(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, 
   }
 }
 
+// The queue kernel carries the approximated step and the forced two-pass
+// route only when a request of the launch needs them.
+inline bool queue_full(const LaunchCfg& cfg) { return cfg.full != 0 || cfg.mode == kModeTwoPass; }
+
 template <int G>
 hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nchunks, uint32_t* head,
                     const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
-  auto k = k_walk_queue<G>;
+  auto k = queue_full(cfg) ? k_walk_queue<G, true> : k_walk_queue<G, false>;
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, ((uint64_t)nchunks + gpb - 1) / gpb, di);
@@ -815,9 +819,10 @@ int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks)
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   const uint64_t work = ((uint64_t)nchunks + gpb - 1) / gpb;
-  if (G == 16) return grid_for(k_walk_queue<16>, lds, work, di);
-  if (G == 32) return grid_for(k_walk_queue<32>, lds, work, di);
-  return grid_for(k_walk_queue<64>, lds, work, di);
+  const bool full = queue_full(cfg);
+  if (G == 16) return grid_for(full ? k_walk_queue<16, true> : k_walk_queue<16, false>, lds, work, di);
+  if (G == 32) return grid_for(full ? k_walk_queue<32, true> : k_walk_queue<32, false>, lds, work, di);
+  return grid_for(full ? k_walk_queue<64, true> : k_walk_queue<64, false>, lds, work, di);
 }
 
 hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint32_t nchunks,
