@@ -453,13 +453,11 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
               const uint64_t m = grp_ballot<G>(hit, gbase);
               if (m == 0) return;
               if (hit) {
+                // a listed position gets its weight after the route (below);
+                // a hit beyond the page adds its weight to the first pass's sum now
                 const uint32_t idx = stored + (uint32_t)__popcll(m & lt_mask);
-                const uint32_t wv = (uint32_t)Wv(pos);
-                if (first) acc += wv;
-                if (idx < (uint32_t)cap) {
-                  lpos[idx] = pos;
-                  lw[idx] = wv;
-                }
+                if (idx < (uint32_t)cap) lpos[idx] = pos;
+                else if (first) acc += (uint32_t)Wv(pos);
               }
               const uint32_t nh = (uint32_t)__popcll(m);
               const uint32_t room = (uint32_t)cap - stored;
@@ -582,6 +580,19 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   append(act && !isret && in_t, j, c);
                 }
                 if (first) staged = stg;
+              }
+              // Weights of the page's positions: one gather over the list, off the
+              // chain of dependent loads of the route's rounds.
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+              for (uint32_t k = gl; k < stored; k += 2 * G) {
+                const uint32_t k2 = k + G;
+                const bool two = k2 < stored;
+                const uint32_t w1 = (uint32_t)Wv(lpos[k]);
+                const uint32_t w2 = two ? (uint32_t)Wv(lpos[k2]) : 0u;
+                lw[k] = w1;
+                if (two) lw[k2] = w2;
+                if (first) acc += (uint64_t)w1 + w2;
               }
               // the page is read by other lanes of the group
               __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
