@@ -229,4 +229,24 @@ __device__ __forceinline__ uint32_t lower_bound_i32(const int32_t* D, uint32_t d
   return lo;
 }
 
+// Floor search in a strictly increasing array: the largest index b in
+// [base, base + len) with A[b] <= x, given vb = A[base] <= x (or base = 0 and
+// vb = A[0] > x, when the answer stays base with a value other than x), and
+// that value.  A membership test compares the value, so the found entry is
+// never read a second time.  Needs len >= 1.
+__device__ __forceinline__ uint32_t floor_search(const int32_t* A, uint32_t base, uint32_t len, int32_t vb,
+                                                 int32_t x, int32_t& val) {
+  while (len > 1) {
+    const uint32_t half = len >> 1;
+    const int32_t v = A[base + half];
+    if (v <= x) {
+      base += half;
+      vb = v;
+    }
+    len -= half;
+  }
+  val = vb;
+  return base;
+}
+
 }  // namespace n2v

@@ -89,8 +89,9 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
           if (total == 0) break;  // every candidate has weight zero
           j = upper_bound_interp(R + lo, d, scale_draw(r, total), total);
         } else {
-          const uint32_t pt = lower_bound_i32(D + lo, d, t);
-          const bool has_t = pt < d && D[lo + pt] == t;
+          int32_t vt;
+          const uint32_t pt = floor_search(D + lo, 0u, d, D[lo], t, vt);
+          const bool has_t = vt == t;
           uint64_t wt = 0;
           if (has_t) wt = (MODE == kRetW) ? (uint64_t)a.g.W[lo + pt] : 1ull;
           const uint64_t S =
@@ -130,23 +131,17 @@ __global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a) {
 }
 
 __device__ __forceinline__ bool lds_contains(const int32_t* A, uint32_t n, int32_t x) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if (A[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo < n && A[lo] == x;
+  if (n == 0) return false;
+  int32_t val;
+  floor_search(A, 0u, n, A[0], x, val);
+  return val == x;
 }
 
 __device__ __forceinline__ bool global_contains(const int32_t* __restrict__ A, uint32_t n, int32_t x) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = lo + ((hi - lo) >> 1);
-    if (A[mid] < x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo < n && A[lo] == x;
+  if (n == 0) return false;
+  int32_t val;
+  floor_search(A, 0u, n, A[0], x, val);
+  return val == x;
 }
 
 // ---------------------------------------------------------------------------
@@ -200,22 +195,27 @@ __device__ __forceinline__ void load_splitters(const int32_t* __restrict__ A, ui
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// First index j in [0, n) with A[j] >= y (n if none), searching only the
-// slice between the splitters around y.
+// Floor search of y in A[0, n) (n >= G) that starts from the slice between
+// the splitters around y: the splitter below y is the slice's first entry, so
+// its value comes from LDS.  Returns the position and its value as
+// floor_search does (value != y when y is not in A).
 template <int G>
-__device__ __forceinline__ uint32_t lower_bound_split(const int32_t* __restrict__ A, uint32_t n,
-                                                      const int32_t* spl, int32_t y) {
-  // largest splitter index l with spl[l] <= y (spl[0] = A[0]); none -> y < A[0]
-  int lo = 0, hi = G;  // first l with spl[l] > y lies in [lo, hi]
+__device__ __forceinline__ uint32_t split_floor(const int32_t* __restrict__ A, uint32_t n, const int32_t* spl,
+                                                int32_t y, int32_t& val) {
+  // first splitter index l with spl[l] > y (spl[0] = A[0]); 0 -> y < A[0]
+  int lo = 0, hi = G;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (spl[mid] <= y) lo = mid + 1;
     else hi = mid;
   }
-  if (lo == 0) return 0;
+  if (lo == 0) {
+    val = spl[0];  // above y
+    return 0;
+  }
   const uint32_t b = (uint32_t)(((uint64_t)(lo - 1) * n) / G);
   const uint32_t e = lo < G ? (uint32_t)(((uint64_t)lo * n) / G) : n;
-  return b + lower_bound_i32(A + b, e - b, y);
+  return floor_search(A, b, e - b, spl[lo - 1], y, val);
 }
 
 template <int G, bool WEIGHTED, typename RT, bool FULL>
@@ -359,8 +359,9 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             if (x == t) return wt * P16;
             bool common;
             if (split_t) {
-              const uint32_t q = lower_bound_split<G>(D + tlo, td, win, x);
-              common = q < td && D[tlo + q] == x;
+              int32_t val;
+              split_floor<G>(D + tlo, td, win, x, val);
+              common = val == x;
             } else {
               common = member(x);
             }
@@ -486,8 +487,9 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   uint32_t pos = 0;
                   bool hit = false;
                   if (act) {
-                    pos = split ? lower_bound_split<G>(D + lo, d, win, y) : lower_bound_i32(D + lo, d, y);
-                    hit = pos < d && D[lo + pos] == y;
+                    int32_t val;
+                    pos = split ? split_floor<G>(D + lo, d, win, y, val) : floor_search(D + lo, 0u, d, D[lo], y, val);
+                    hit = val == y;
                   }
                   const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
                   if (mt) {
@@ -571,8 +573,12 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                     in_t = act && !isret && lds_contains(cur, td, x);
                   } else {
                     if (split) {
-                      const uint32_t q = act && !isret ? lower_bound_split<G>(D + tlo, td, win, x) : td;
-                      in_t = q < td && D[tlo + q] == x;
+                      in_t = false;
+                      if (act && !isret) {
+                        int32_t val;
+                        split_floor<G>(D + tlo, td, win, x, val);
+                        in_t = val == x;
+                      }
                     } else {
                       in_t = act && !isret && global_contains(D + tlo, td, x);
                     }
