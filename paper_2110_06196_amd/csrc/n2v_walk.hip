@@ -699,7 +699,9 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
 template <int G, bool WEIGHTED, typename RT, bool FULL>
 __global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 7 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
   extern __shared__ int32_t lds[];
-  const int gib = threadIdx.x / G;
+  // with one walker per wavefront the group index is uniform: say so, so that
+  // per-walker state (walk index, counters, draws) lives in scalar registers
+  const int gib = G == 64 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64u) : (int)(threadIdx.x / G);
   const int gpb = blockDim.x / G;
   int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap, G);
   const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
