@@ -541,13 +541,25 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
 }
 
 template <bool WEIGHTED, typename RT>
-__global__ __launch_bounds__(256) void k_walk_n2v_ef(WalkArgs a, EFDev e) {
+__global__ __launch_bounds__(256) void k_walk_n2v_ef(WalkArgs a, EFDev e, unsigned long long* ctr, uint32_t chunk) {
   __shared__ int32_t tiles[4][2][kEfTile];
   const int gl = threadIdx.x & 63;
-  const int wv = threadIdx.x / 64;
+  // the wave index is uniform: per-walker state goes to scalar registers
+  const int wv = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
   const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
-  for (uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / 64) + wv; w < a.nwalks; w += waves)
+  // with a launch counter waves take `chunk` walks at a time, else fixed shares
+  uint64_t w = ctr ? 0 : (uint64_t)blockIdx.x * (blockDim.x / 64) + wv, end = 0;
+  while (true) {
+    if (ctr && w >= end) {
+      unsigned long long c = 0;
+      if (gl == 0) c = atomicAdd(ctr, (unsigned long long)chunk);
+      w = wave_read_u64((uint64_t)c, 0);
+      end = min(w + chunk, a.nwalks);
+    }
+    if (w >= a.nwalks) break;
     wave_walk_ef<WEIGHTED, RT>(a, e, w, gl, tiles[wv][0], tiles[wv][1]);
+    w += ctr ? 1 : waves;
+  }
 }
 
 // Scale-free negatives: the node owning entry T of the edge list is the
@@ -666,9 +678,16 @@ hipError_t launch_walks_ef(const WalkArgs& a, Path path, const EFDev& e, const D
       break;
     default: {
       const dim3 wave_grid(ef_blocks(a.nwalks * 64, di));
-      if (!weighted) hipLaunchKernelGGL((k_walk_n2v_ef<false, uint32_t>), wave_grid, dim3(256), 0, st, a, e);
-      else if (r64) hipLaunchKernelGGL((k_walk_n2v_ef<true, uint64_t>), wave_grid, dim3(256), 0, st, a, e);
-      else hipLaunchKernelGGL((k_walk_n2v_ef<true, uint32_t>), wave_grid, dim3(256), 0, st, a, e);
+      const uint32_t chunk = walk_chunk(a.nwalks, (uint64_t)wave_grid.x * 4);
+      return with_walk_counter(di, st, [&](unsigned long long* ctr) {
+        if (!weighted)
+          hipLaunchKernelGGL((k_walk_n2v_ef<false, uint32_t>), wave_grid, dim3(256), 0, st, a, e, ctr, chunk);
+        else if (r64)
+          hipLaunchKernelGGL((k_walk_n2v_ef<true, uint64_t>), wave_grid, dim3(256), 0, st, a, e, ctr, chunk);
+        else
+          hipLaunchKernelGGL((k_walk_n2v_ef<true, uint32_t>), wave_grid, dim3(256), 0, st, a, e, ctr, chunk);
+        return hipGetLastError();
+      });
     }
   }
   return hipGetLastError();

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <mutex>
+
 namespace n2v {
 
 // Resident graph: borrowed CSR plus library-owned derived arrays.
@@ -79,6 +82,35 @@ struct DevInfo {
   int cus = 0;
   size_t lds_per_block_max = 0;
 };
+
+// Walk counters: every stream of a device has one, allocated at the stream's
+// first launch and kept until the process ends.  counter_slot returns it, or
+// null (the kernels then use fixed shares) when the stream is being captured
+// or no counter can be had.
+unsigned long long* counter_slot(const DevInfo& di, hipStream_t st);
+// Enqueues a kernel on st that zeroes *c.
+void reset_counter(unsigned long long* c, hipStream_t st);
+std::mutex& counter_mutex();
+
+// Walks a group takes from the launch counter at a time: one while a group's
+// share of the launch is small (a grid sized to the walks keeps every group
+// busy), up to 8 for long launches (fewer atomics, a tail of a few walks).
+inline uint32_t walk_chunk(uint64_t nwalks, uint64_t groups) {
+  const uint64_t share = groups ? nwalks / groups : nwalks;
+  return (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, share / 64));
+}
+
+// Runs launch(counter) with the stream's counter zeroed right before it on the
+// stream: the reset and the launch are enqueued under one lock, so launches
+// from several threads onto one stream cannot interleave between them.
+template <typename F>
+hipError_t with_walk_counter(const DevInfo& di, hipStream_t st, F&& launch) {
+  unsigned long long* c = counter_slot(di, st);
+  if (!c) return launch((unsigned long long*)nullptr);
+  std::lock_guard<std::mutex> lk(counter_mutex());
+  reset_counter(c, st);
+  return launch(c);
+}
 
 hipError_t launch_walks(const WalkArgs& a, Path path, const LaunchCfg& cfg, const DevInfo& di,
                         hipStream_t st);

@@ -149,6 +149,7 @@ __device__ __forceinline__ bool global_contains(const int32_t* __restrict__ A, u
 // ---------------------------------------------------------------------------
 enum { kModeAuto = 0, kModeTwoPass = 1, kModeProbe = 2, kModeStream = 3, kModeMerge = 4 };
 
+
 __device__ __forceinline__ uint32_t ceil_log2p1(uint32_t x) {  // ceil(log2(x + 1))
   return 32u - (uint32_t)__clz(x);
 }
@@ -697,16 +698,32 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
 }
 
 template <int G, bool WEIGHTED, typename RT, bool FULL>
-__global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 7 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob) {
+__global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 7 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
+                                                                                   unsigned long long* ctr, uint32_t chunk) {
   extern __shared__ int32_t lds[];
   // with one walker per wavefront the group index is uniform: say so, so that
   // per-walker state (walk index, counters, draws) lives in scalar registers
   const int gib = G == 64 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64u) : (int)(threadIdx.x / G);
   const int gpb = blockDim.x / G;
   int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap, G);
+  // With a launch counter, groups take `chunk` walks at a time (walk costs are
+  // heavy-tailed: fixed shares leave a long tail); without, fixed shares.
+  const int gl = (threadIdx.x & 63) & (G - 1);
   const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
-  for (uint64_t w = (uint64_t)blockIdx.x * gpb + gib; w < a.nwalks; w += ngroups)
+  uint64_t w = ctr ? 0 : (uint64_t)blockIdx.x * gpb + gib, e = 0;
+  while (true) {
+    if (ctr) {
+      if (w >= e) {
+        unsigned long long c = 0;
+        if (gl == 0) c = atomicAdd(ctr, (unsigned long long)chunk);
+        w = grp_bcast<G>((uint64_t)c, 0);
+        e = min(w + chunk, a.nwalks);
+      }
+    }
+    if (w >= a.nwalks) break;
     group_walk<G, WEIGHTED, RT, FULL>(a, w, mem, tile, cap, mode_knob);
+    w += ctr ? 1 : ngroups;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -758,6 +775,48 @@ __global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkA
 }
 
 __global__ void k_reset_counter(uint32_t* head) { *head = 0u; }
+__global__ void k_reset_counter64(unsigned long long* c) { *c = 0ull; }
+
+}  // namespace
+
+unsigned long long* counter_slot(const DevInfo& di, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, unsigned long long*> slot;
+  static std::map<int, std::pair<unsigned long long*, int>> slab;  // device -> (slab, slots used)
+  constexpr int kSlab = 512;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(di.device, st);
+  auto it = slot.find(key);
+  if (it != slot.end()) return it->second;
+  auto& sb = slab[di.device];
+  if (sb.first == nullptr || sb.second == kSlab) {
+    void* p = nullptr;
+    if (hipMalloc(&p, kSlab * sizeof(unsigned long long)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    sb = std::make_pair((unsigned long long*)p, 0);
+  }
+  unsigned long long* c = sb.first + sb.second++;
+  slot.emplace(key, c);
+  return c;
+}
+
+void reset_counter(unsigned long long* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter64, dim3(1), dim3(1), 0, st, c);
+}
+
+std::mutex& counter_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
+namespace {
 
 // Grid size: enough blocks to fill every CU at the kernel's occupancy, never
 // more than the work needs (the kernels loop over walkers).
@@ -799,8 +858,11 @@ hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hi
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
-  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cfg.mode);
-  return hipGetLastError();
+  return with_walk_counter(di, st, [&](unsigned long long* ctr) {
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cfg.mode, ctr,
+                       walk_chunk(a.nwalks, (uint64_t)blocks * gpb));
+    return hipGetLastError();
+  });
 }
 
 template <bool WEIGHTED, typename RT>

@@ -100,6 +100,46 @@ def test_tuning_points_and_specialisations_identical():
         _tuning_sweep(O, D, ww, rows, 30, cases, grid)
 
 
+def test_walk_counters_streams_and_threads():
+    """node2vec launches hand out walks from a per-stream counter that a kernel
+    zeroes before each launch: back-to-back launches on one stream, launches on
+    several streams at once and four host threads launching onto one stream
+    all give the oracle's walks."""
+    import threading
+    O, D, W = synth.chung_lu(5000, 60000, 2.2, 20.0, 2000.0, (1, 100), seed=31)
+    n = len(O) - 1
+    g, keep = upload(O, D, W)
+    S = torch.arange(n, dtype=torch.int32, device="cuda")
+    args = (g, S, 2, 30, 0.25, 4.0, 5)
+    ref, rlens = n2v.n2v_walks_node2vec(*args)
+    torch.cuda.synchronize()
+    rows = np.arange(0, 2 * n, 13)
+    Yo, lo = oracle.walks(O, D, W, np.arange(n), 2, 30, NV, 0.25, 4.0, 5, 0, rows=rows)
+    assert np.array_equal(ref.cpu().numpy()[rows], Yo) and np.array_equal(rlens.cpu().numpy()[rows], lo)
+    outs = [n2v.n2v_walks_node2vec(*args) for _ in range(3)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for st in streams:
+        with torch.cuda.stream(st):
+            outs.append(n2v.n2v_walks_node2vec(*args, stream=st))
+    shared = torch.cuda.Stream()
+    res = [None] * 4
+
+    def worker(i):
+        with torch.cuda.stream(shared):
+            res[i] = n2v.n2v_walks_node2vec(*args, stream=shared)
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    for i, (Y, L) in enumerate(outs + res):
+        assert torch.equal(Y, ref) and torch.equal(L, rlens), i
+    n2v.n2v_graph_release(g)
+    del keep
+
+
 def test_hub_rows_all_routes():
     """Hubs of degree ~1e4: many chunks per block in the two-pass route, long
     probe and stream lists, G-ary searches over long segments."""
