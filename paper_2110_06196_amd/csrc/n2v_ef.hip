@@ -315,7 +315,21 @@ __device__ __forceinline__ void lane_walk_ef(const WalkArgs& a, const EFDev& e, 
 }
 
 template <int MODE, typename RT>
-__global__ __launch_bounds__(256) void k_walk_lane_ef(WalkArgs a, EFDev e) {
+__global__ __launch_bounds__(256) void k_walk_lane_ef(WalkArgs a, EFDev e, unsigned long long* ctr, uint32_t chunk) {
+  if (ctr) {
+    // a wave takes 64 * chunk walks at a time from the launch counter
+    const int lane = threadIdx.x & 63;
+    const uint64_t span = 64ull * chunk;
+    while (true) {
+      unsigned long long c = 0;
+      if (lane == 0) c = atomicAdd(ctr, (unsigned long long)span);
+      const uint64_t base = wave_read_u64((uint64_t)c, 0);
+      if (base >= a.nwalks) break;
+      const uint64_t end = min(base + span, a.nwalks);
+      for (uint64_t w = base + lane; w < end; w += 64) lane_walk_ef<MODE, RT>(a, e, w);
+    }
+    return;
+  }
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwalks; w += stride)
     lane_walk_ef<MODE, RT>(a, e, w);
@@ -665,17 +679,20 @@ hipError_t launch_walks_ef(const WalkArgs& a, Path path, const EFDev& e, const D
   const bool weighted = a.g.R != nullptr;
   const bool r64 = a.g.r_bytes == 8;
   const dim3 lane_grid(ef_blocks(a.nwalks, di));
+  const uint32_t lane_chunk = walk_chunk(a.nwalks / 64, (uint64_t)lane_grid.x * 4);
+  auto lane = [&](auto kernel) {
+    return with_walk_counter(di, st, [&](unsigned long long* ctr) {
+      hipLaunchKernelGGL(kernel, lane_grid, dim3(256), 0, st, a, e, ctr, lane_chunk);
+      return hipGetLastError();
+    });
+  };
   switch (path) {
     case Path::kFirstOrder:
-      if (!weighted) hipLaunchKernelGGL((k_walk_lane_ef<kEfFoUnw, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
-      else if (r64) hipLaunchKernelGGL((k_walk_lane_ef<kEfFoW, uint64_t>), lane_grid, dim3(256), 0, st, a, e);
-      else hipLaunchKernelGGL((k_walk_lane_ef<kEfFoW, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
-      break;
+      if (!weighted) return lane(k_walk_lane_ef<kEfFoUnw, uint32_t>);
+      return r64 ? lane(k_walk_lane_ef<kEfFoW, uint64_t>) : lane(k_walk_lane_ef<kEfFoW, uint32_t>);
     case Path::kReturnOnly:
-      if (!weighted) hipLaunchKernelGGL((k_walk_lane_ef<kEfRetUnw, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
-      else if (r64) hipLaunchKernelGGL((k_walk_lane_ef<kEfRetW, uint64_t>), lane_grid, dim3(256), 0, st, a, e);
-      else hipLaunchKernelGGL((k_walk_lane_ef<kEfRetW, uint32_t>), lane_grid, dim3(256), 0, st, a, e);
-      break;
+      if (!weighted) return lane(k_walk_lane_ef<kEfRetUnw, uint32_t>);
+      return r64 ? lane(k_walk_lane_ef<kEfRetW, uint64_t>) : lane(k_walk_lane_ef<kEfRetW, uint32_t>);
     default: {
       const dim3 wave_grid(ef_blocks(a.nwalks * 64, di));
       const uint32_t chunk = walk_chunk(a.nwalks, (uint64_t)wave_grid.x * 4);

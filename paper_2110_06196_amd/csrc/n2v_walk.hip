@@ -124,7 +124,21 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
 }
 
 template <int MODE, typename RT>
-__global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a) {
+__global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a, unsigned long long* ctr, uint32_t chunk) {
+  if (ctr) {
+    // a wave takes 64 * chunk walks at a time from the launch counter
+    const int lane = threadIdx.x & 63;
+    const uint64_t span = 64ull * chunk;
+    while (true) {
+      unsigned long long c = 0;
+      if (lane == 0) c = atomicAdd(ctr, (unsigned long long)span);
+      const uint64_t base = wave_read_u64((uint64_t)c, 0);
+      if (base >= a.nwalks) break;
+      const uint64_t end = min(base + span, a.nwalks);
+      for (uint64_t w = base + lane; w < end; w += 64) lane_walk<MODE, RT>(a, w);
+    }
+    return;
+  }
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwalks; w += stride)
     lane_walk<MODE, RT>(a, w);
@@ -847,8 +861,11 @@ template <int MODE, typename RT>
 hipError_t go_lane(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   auto k = k_walk_lane<MODE, RT>;
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, 0, (a.nwalks + 255) / 256, di);
-  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, a);
-  return hipGetLastError();
+  return with_walk_counter(di, st, [&](unsigned long long* ctr) {
+    // a wave's share in units of 64 walks decides its chunk
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, st, a, ctr, walk_chunk(a.nwalks / 64, (uint64_t)blocks * 4));
+    return hipGetLastError();
+  });
 }
 
 template <int G, bool WEIGHTED, typename RT>
