@@ -92,7 +92,7 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
   // list overflow costs a two-pass stream of the row; a miss in the tile only
   // a bisection in global memory); 8 blocks of 256 threads fit one CU.
   c.lds_tile = c.lanes_per_walker == 64 ? 64 : (c.lanes_per_walker == 32 ? 64 : 32);
-  c.list_cap = c.lanes_per_walker == 64 ? 576 : (c.lanes_per_walker == 32 ? 256 : 128);
+  c.list_cap = c.lanes_per_walker == 64 ? 512 : (c.lanes_per_walker == 32 ? 256 : 128);
   c.mode = 0;
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_tune_set) {
