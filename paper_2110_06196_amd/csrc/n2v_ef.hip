@@ -315,7 +315,7 @@ __device__ __forceinline__ void lane_walk_ef(const WalkArgs& a, const EFDev& e, 
 }
 
 template <int MODE, typename RT>
-__global__ __launch_bounds__(256) void k_walk_lane_ef(WalkArgs a, EFDev e, unsigned long long* ctr, uint32_t chunk) {
+__global__ __launch_bounds__(256, 8) void k_walk_lane_ef(WalkArgs a, EFDev e, unsigned long long* ctr, uint32_t chunk) {
   if (ctr) {
     // a wave takes 64 * chunk walks at a time from the launch counter
     const int lane = threadIdx.x & 63;
@@ -555,7 +555,7 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
 }
 
 template <bool WEIGHTED, typename RT>
-__global__ __launch_bounds__(256) void k_walk_n2v_ef(WalkArgs a, EFDev e, unsigned long long* ctr, uint32_t chunk) {
+__global__ __launch_bounds__(256, 8) void k_walk_n2v_ef(WalkArgs a, EFDev e, unsigned long long* ctr, uint32_t chunk) {
   __shared__ int32_t tiles[4][2][kEfTile];
   const int gl = threadIdx.x & 63;
   // the wave index is uniform: per-walker state goes to scalar registers

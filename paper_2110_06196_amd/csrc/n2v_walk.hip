@@ -712,7 +712,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
 }
 
 template <int G, bool WEIGHTED, typename RT, bool FULL>
-__global__ __launch_bounds__(256, (G == 64 && WEIGHTED && sizeof(RT) == 4) ? 8 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
+__global__ __launch_bounds__(256, G == 64 ? 8 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
                                                                                    unsigned long long* ctr, uint32_t chunk) {
   extern __shared__ int32_t lds[];
   // with one walker per wavefront the group index is uniform: say so, so that
