@@ -40,6 +40,7 @@
 #include "n2v_device.hpp"
 #include "n2v_internal.hpp"
 
+#include <cstddef>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -760,6 +761,73 @@ __device__ __forceinline__ void lane_dispatch(const WalkArgs& a, uint64_t w) {
   }
 }
 
+// The batched kernel reads its requests from a table in device memory.  A
+// pointer read from memory carries no address space, so loads through it
+// would compile to flat loads (which also wait on the LDS counter).  Every
+// array a request points to is in global memory: this mirror of WalkArgs,
+// with the same layout, types the pointers so, and the kernel converts them
+// once per chunk.
+#define N2V_GLOBAL __attribute__((address_space(1)))
+struct GraphDevG {
+  const N2V_GLOBAL uint64_t* O;
+  const N2V_GLOBAL int32_t* D;
+  const N2V_GLOBAL uint32_t* W;
+  const N2V_GLOBAL void* R;
+  uint32_t r_bytes;
+  int64_t n;
+  uint64_t m;
+  const N2V_GLOBAL uint4* NR;
+};
+struct WalkArgsG {
+  GraphDevG g;
+  const N2V_GLOBAL int32_t* starts;
+  uint64_t ns;
+  uint64_t nwalks;
+  uint32_t L;
+  uint32_t second_order;
+  uint32_t P16, Q16;
+  uint64_t seed;
+  uint64_t wid_base;
+  N2V_GLOBAL int32_t* Y;
+  N2V_GLOBAL int32_t* lens;
+  uint32_t path;
+  uint32_t k_approx;
+  N2V_GLOBAL unsigned long long* steps;
+};
+static_assert(sizeof(WalkArgsG) == sizeof(WalkArgs) && offsetof(WalkArgsG, g.NR) == offsetof(WalkArgs, g.NR) &&
+                  offsetof(WalkArgsG, starts) == offsetof(WalkArgs, starts) &&
+                  offsetof(WalkArgsG, seed) == offsetof(WalkArgs, seed) && offsetof(WalkArgsG, Y) == offsetof(WalkArgs, Y) &&
+                  offsetof(WalkArgsG, path) == offsetof(WalkArgs, path) &&
+                  offsetof(WalkArgsG, steps) == offsetof(WalkArgs, steps),
+              "WalkArgsG mirrors WalkArgs");
+
+__device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
+  WalkArgs a;
+  a.g.O = (const uint64_t*)r.g.O;
+  a.g.D = (const int32_t*)r.g.D;
+  a.g.W = (const uint32_t*)r.g.W;
+  a.g.R = (const void*)r.g.R;
+  a.g.r_bytes = r.g.r_bytes;
+  a.g.n = r.g.n;
+  a.g.m = r.g.m;
+  a.g.NR = (const uint4*)r.g.NR;
+  a.starts = (const int32_t*)r.starts;
+  a.ns = r.ns;
+  a.nwalks = r.nwalks;
+  a.L = r.L;
+  a.second_order = r.second_order;
+  a.P16 = r.P16;
+  a.Q16 = r.Q16;
+  a.seed = r.seed;
+  a.wid_base = r.wid_base;
+  a.Y = (int32_t*)r.Y;
+  a.lens = (int32_t*)r.lens;
+  a.path = r.path;
+  a.k_approx = r.k_approx;
+  a.steps = (unsigned long long*)r.steps;
+  return a;
+}
+
 template <int G, bool FULL>
 __global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkArgs* __restrict__ reqs,
                                                     const QueueChunk* __restrict__ chunks, uint32_t nchunks,
@@ -775,7 +843,7 @@ __global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkA
     c = (uint32_t)grp_bcast_i32<G>((int32_t)c, 0);
     if (c >= nchunks) break;  // every group exits once the queue is drained
     const QueueChunk ch = chunks[c];
-    const WalkArgs a = reqs[ch.req];
+    const WalkArgs a = from_global(((const WalkArgsG*)reqs)[ch.req]);
     if (a.path != (uint32_t)Path::kGeneric) {
       for (uint64_t w = ch.w0 + (uint64_t)gl; w < ch.w1; w += G) lane_dispatch<G>(a, w);
     } else if (a.g.W == nullptr) {
