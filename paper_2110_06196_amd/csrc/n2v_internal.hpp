@@ -67,9 +67,9 @@ struct LaunchCfg {
 };
 
 // LDS words per walker group of g lanes: two staging tiles of the previous
-// row, the common-neighbour list (positions, weights) and a g-entry merge
-// window.
-__host__ __device__ constexpr int group_lds_words(int tile, int cap, int g) { return 2 * tile + 2 * cap + g; }
+// row, the common-neighbour list (positions, weights) and a 2g-entry merge
+// window (also the splitters of a long row).
+__host__ __device__ constexpr int group_lds_words(int tile, int cap, int g) { return 2 * tile + 2 * cap + 2 * g; }
 
 // LDS bytes of a 256-thread block for a launch shape.
 inline size_t block_lds_bytes(int lanes_per_walker, int tile, int cap) {

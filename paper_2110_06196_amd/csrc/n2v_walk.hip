@@ -451,7 +451,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             const uint64_t stream = (uint64_t)((d + G - 1) / G) *
                                         (100u + (t_in_lds ? 15u * ceil_log2p1(td) : glob(td))) +
                                     (!t_in_lds && td >= 4u * G ? 100u : 0u);
-            const uint64_t merge = (uint64_t)(((uint64_t)d + td + G - 1) / G) * (t_in_lds ? 130u : 220u);
+            const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) * (t_in_lds ? 150u : 240u);
             mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
                                   : (stream <= merge ? kModeStream : kModeMerge);
           }
@@ -516,11 +516,14 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   append(hit && !tkey && y != t, pos, c);
                 }
               } else if (mode == kModeMerge) {
-                // co-iterate N(v) (keys, global) and N(t) (B): invariant
-                // "every element of B before ib is below N(v)[ia]"; a window
-                // of G elements of B goes to LDS, every lane whose candidate is
-                // at most the window's last element is decided by bisecting
-                // the window; each round advances ia by G or ib by G.
+                // co-iterate N(v) (candidates, global) and N(t) (B): invariant
+                // "every element of B before ib is below N(v)[ia]".  A round
+                // stages 2G elements of B in LDS, takes 2G candidates (two per
+                // lane), decides every candidate that is at most the window's
+                // last element by bisecting the window, and advances ia past
+                // the decided candidates, or ib by 2G when some candidate lies
+                // beyond the window.
+                constexpr uint32_t W2 = 2u * G;
                 const bool stg = first && d <= (uint32_t)tile;
                 auto Bv = [&](uint32_t k) -> int32_t { return t_in_lds ? cur[k] : D[tlo + k]; };
                 uint32_t ia = from, ib = 0;
@@ -530,36 +533,44 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                 }
                 while (ia < d) {
                   if (!first && stored >= (uint32_t)cap) break;
-                  const uint32_t j = ia + gl;
-                  const bool act = j < d;
-                  int32_t x = 0x7FFFFFFF;
-                  if (act) {
-                    x = D[lo + j];
-                    if (stg) nxt[j] = x;
+                  const uint32_t j0 = ia + gl, j1 = j0 + G;
+                  const bool act0 = j0 < d, act1 = j1 < d;
+                  int32_t x0 = 0x7FFFFFFF, x1 = 0x7FFFFFFF;
+                  if (act0) x0 = D[lo + j0];
+                  if (act1) x1 = D[lo + j1];
+                  const uint32_t nb = ib < td ? min(W2, td - ib) : 0u;
+                  const int32_t b0 = (uint32_t)gl < nb ? Bv(ib + gl) : 0x7FFFFFFF;
+                  const int32_t b1 = (uint32_t)gl + G < nb ? Bv(ib + G + gl) : 0x7FFFFFFF;
+                  if (stg) {
+                    if (act0) nxt[j0] = x0;
+                    if (act1) nxt[j1] = x1;
                   }
-                  const uint32_t nb = ib < td ? min((uint32_t)G, td - ib) : 0u;
-                  const int32_t bval = (uint32_t)gl < nb ? Bv(ib + gl) : 0x7FFFFFFF;
-                  win[gl] = bval;
+                  win[gl] = b0;
+                  win[G + gl] = b1;
                   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                  // B beyond this window is empty when nb < G: then every candidate is decided
-                  const int32_t blast = nb == (uint32_t)G ? grp_bcast_i32<G>(bval, G - 1) : 0x7FFFFFFF;
-                  const bool res = act && x <= blast;
-                  const bool isret = res && x == t;
-                  const uint64_t mt = grp_ballot<G>(isret, gbase);
-                  if (mt) {
+                  // B beyond this window is empty when nb < 2G: then every candidate is decided
+                  const int32_t blast = nb == W2 ? grp_bcast_i32<G>(b1, G - 1) : 0x7FFFFFFF;
+                  const bool res0 = act0 && x0 <= blast, res1 = act1 && x1 <= blast;
+                  const bool ret0 = res0 && x0 == t, ret1 = res1 && x1 == t;
+                  const uint64_t mt0 = grp_ballot<G>(ret0, gbase), mt1 = grp_ballot<G>(ret1, gbase);
+                  if (mt0 | mt1) {
                     has_t = true;
-                    pt = ia + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
+                    pt = mt0 ? ia + (uint32_t)(__ffsll((unsigned long long)mt0) - 1)
+                             : ia + G + (uint32_t)(__ffsll((unsigned long long)mt1) - 1);
                   }
-                  const bool in_t = res && !isret && nb > 0 && lds_contains(win, nb, x);
-                  append(in_t, j, ia);
-                  const uint32_t nact = min((uint32_t)G, d - ia);
-                  const uint32_t nres = (uint32_t)__popcll(grp_ballot<G>(res, gbase));
+                  const bool in0 = res0 && !ret0 && nb > 0 && lds_contains(win, nb, x0);
+                  const bool in1 = res1 && !ret1 && nb > 0 && lds_contains(win, nb, x1);
+                  append(in0, j0, ia);
+                  append(in1, j1, ia + G);
+                  const uint32_t nact = min(W2, d - ia);
+                  const uint32_t nres = (uint32_t)__popcll(grp_ballot<G>(res0, gbase)) +
+                                        (uint32_t)__popcll(grp_ballot<G>(res1, gbase));
                   if (nres == nact) {
                     ia += nact;
                   } else {
-                    ia += nres;  // decided lanes are a prefix: the candidates are sorted
-                    ib += (uint32_t)G;
+                    ia += nres;  // decided candidates are a prefix: the candidates are sorted
+                    ib += W2;
                   }
                   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
