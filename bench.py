@@ -322,9 +322,10 @@ def algorithmic_bytes(torch, Y, lens, deg, variant: str) -> tuple[int, int]:
       first order, weighted (also node2vec p = q = 1 and the first step of
       every node2vec walk): ceil(log2(d_v + 1)) prefix probes of 4 B;
       node2vec with 1/q != 1, later steps (previous node t, degree d_t): the row
-      sum 4 B, the return weight 4 B, the cheaper classification route
+      sum 4 B, the return weight 4 B, the cheapest classification route
         probe:  N(t) 4 d_t + d_t bisections into N(v), 4 ceil(log2(d_v + 1)) each
         stream: N(v) 4 d_v + d_v bisections into N(t), 4 ceil(log2(d_t + 1)) each
+        merge:  both rows once, 4 d_v + 4 d_t
       and the final search over the prefix, 4 ceil(log2(d_v + 1)).
       (Weights and prefix entries of common neighbours, a few per step, and
       reuse of N(t) from LDS are not counted.)
@@ -344,7 +345,8 @@ def algorithmic_bytes(torch, Y, lens, deg, variant: str) -> tuple[int, int]:
             lv2 = lv[:, 1:]
             probe = 4 * dt + 4 * dt * lv2
             stream = 4 * dv2 + 4 * dv2 * _clog2p1(dt, torch)
-            b2 = 24 + 8 + torch.minimum(probe, stream) + 4 * lv2
+            merge = 4 * dv2 + 4 * dt
+            b2 = 24 + 8 + torch.minimum(torch.minimum(probe, stream), merge) + 4 * lv2
             b = torch.cat([b[:, :1], b2], dim=1)
         total += int((b * taken).sum().item())
     return steps, total

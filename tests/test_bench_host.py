@@ -37,10 +37,16 @@ def test_algorithmic_bytes_hand_count():
     assert fo == c(1) + c(3) + c(40) + c(40)
     _, gen = bench.algorithmic_bytes(torch, Y, lens, deg, "generic")
     # node2vec: the first step of a walk as first order, later steps
-    # 32 + min(probe, stream) + 4 ceil(log2(d_v + 1)) with t the previous node
+    # 32 + min(probe, stream, merge) + 4 ceil(log2(d_v + 1)) with t the previous node
     L = lambda d: d.bit_length()
-    later = lambda dt, dv: 32 + min(4 * dt + 4 * dt * L(dv), 4 * dv + 4 * dv * L(dt)) + 4 * L(dv)
+    later = lambda dt, dv: 32 + min(4 * dt + 4 * dt * L(dv), 4 * dv + 4 * dv * L(dt), 4 * dv + 4 * dt) + 4 * L(dv)
     assert gen == c(1) + later(1, 3) + later(3, 40) + c(40)
+    # two long rows (d_t = 40, d_v = 50): merging both rows (360 B) beats probing (1120 B)
+    # and streaming (1400 B)
+    Y2 = torch.tensor([[2, 3, 2]], dtype=torch.int32)
+    deg2 = torch.tensor([1, 3, 40, 50], dtype=torch.int64)
+    _, g2 = bench.algorithmic_bytes(torch, Y2, torch.tensor([3], dtype=torch.int32), deg2, "generic")
+    assert g2 == c(40) + 32 + (4 * 50 + 4 * 40) + 4 * L(50)
 
 
 def test_traffic_needs_matching_source_hash(tmp_path):
