@@ -275,6 +275,20 @@ int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weig
     gr->dev.NR = NR;
     gr->owned_bytes += (uint64_t)gr->dev.n * sizeof(uint4);
   }
+  if (node_records) {
+    const uint64_t hbytes = ((gr->n_entries + 31) >> 5) * rb;
+    void* HR = nullptr;
+    e = hipMalloc(&HR, (size_t)hbytes);
+    if (e != hipSuccess) return fail(N2V_ERR_NOMEM, "hipMalloc prefix heads: %s", hipGetErrorString(e));
+    e = launch_prefix_heads(R, rb, gr->n_entries, HR, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      hipFree(HR);
+      return hip_fail(e, "prefix heads");
+    }
+    gr->dev.HR = HR;
+    gr->owned_bytes += hbytes;
+  }
   return N2V_OK;
 }
 
@@ -288,6 +302,7 @@ n2v_graph register_graph(GraphRec* gr) {
 void free_record(GraphRec* gr) {
   if (gr->dev.R) hipFree(const_cast<void*>(gr->dev.R));
   if (gr->dev.NR) hipFree(const_cast<uint4*>(gr->dev.NR));
+  if (gr->dev.HR) hipFree(const_cast<void*>(gr->dev.HR));
   if (gr->neg_guide) hipFree(gr->neg_guide);
   if (gr->ef_mem) hipFree(gr->ef_mem);
   delete gr;

@@ -23,6 +23,11 @@ struct GraphDev {
   // S_v} in one 16-byte record, so a step reads its row's offset, degree and
   // weight sum with one load.  Null otherwise.
   const uint4* NR = nullptr;
+  // Weighted CSR graphs: the prefix at every 32nd entry, HR[i] = R[32 i]
+  // (ceil(m / 32) entries of r_bytes).  A search over a long row first
+  // searches the row's heads, which are contiguous, then one 32-entry block of
+  // R.  Null otherwise.
+  const void* HR = nullptr;
 };
 
 // Which kernel family serves a request.
@@ -126,6 +131,8 @@ hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint
 hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
                                  const uint32_t* W, uint64_t* stats, hipStream_t st);
 hipError_t launch_node_records(const uint64_t* O, int64_t n, const uint32_t* R, uint4* NR, hipStream_t st);
+// HR[i] = R[32 i] for i < ceil(m / 32); R of r_bytes (4 or 8) per entry.
+hipError_t launch_prefix_heads(const void* R, uint32_t r_bytes, uint64_t m, void* HR, hipStream_t st);
 hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,
                              uint32_t r_bytes, hipStream_t st);
 

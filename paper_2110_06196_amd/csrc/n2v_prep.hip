@@ -104,7 +104,27 @@ int prep_blocks(int64_t n) {
   return (int)blocks;
 }
 
+template <typename T>
+__global__ void k_prefix_heads(const T* __restrict__ R, uint64_t nh, T* __restrict__ HR) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += stride) HR[i] = R[i << 5];
+}
+
 }  // namespace
+
+hipError_t launch_prefix_heads(const void* R, uint32_t r_bytes, uint64_t m, void* HR, hipStream_t st) {
+  const uint64_t nh = (m + 31) >> 5;
+  if (nh == 0) return hipSuccess;
+  uint64_t blocks = (nh + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  if (r_bytes == 4)
+    hipLaunchKernelGGL(k_prefix_heads<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, st, (const uint32_t*)R, nh,
+                       (uint32_t*)HR);
+  else
+    hipLaunchKernelGGL(k_prefix_heads<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, st, (const uint64_t*)R, nh,
+                       (uint64_t*)HR);
+  return hipGetLastError();
+}
 
 hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
                                  const uint32_t* W, uint64_t* stats, hipStream_t st) {

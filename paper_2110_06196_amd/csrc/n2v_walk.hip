@@ -191,6 +191,37 @@ __device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl,
   return m ? lo + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
 }
 
+// gary_first over a row of a prefix array V (positions lo + j) with a
+// predicate on (V[lo + j], j), monotone in j, through the row's heads
+// H[b] = V[32 b]: a long range first searches the heads of its whole 32-entry
+// blocks (contiguous: a few lines instead of one line per probe), then the
+// at most 32 entries between the last false head and the first true one.
+template <int G, typename RT, typename P>
+__device__ __forceinline__ uint32_t gary_first_heads(const RT* __restrict__ V, const RT* __restrict__ H, uint64_t lo,
+                                                     uint32_t jlo, uint32_t jhi, int gl, int gbase, P pred) {
+  auto direct = [&](uint32_t j) { return pred((uint64_t)V[lo + j], j); };
+  // a range of more than 64 entries holds at least two heads
+  if (H == nullptr || jhi - jlo <= 64u || jhi - jlo <= 2u * G) return gary_first<G>(jlo, jhi, gl, gbase, direct);
+  const uint64_t a = lo + jlo, e = lo + jhi;
+  const uint64_t hb0 = (a + 31) >> 5, hb1 = (e - 1) >> 5;  // blocks whose head lies in [a, e)
+  const uint32_t nh = (uint32_t)(hb1 - hb0 + 1);
+  const uint32_t k = gary_first<G>(0u, nh, gl, gbase, [&](uint32_t i) {
+    return pred((uint64_t)H[hb0 + i], (uint32_t)(((hb0 + i) << 5) - lo));
+  });
+  uint64_t sb, se;  // the answer is the first true position in [sb, se), or none (jhi)
+  if (k == 0) {
+    sb = a;
+    se = (hb0 << 5) + 1;
+  } else if (k == nh) {
+    sb = (hb1 << 5) + 1;
+    se = e;
+  } else {
+    sb = ((hb0 + k - 1) << 5) + 1;
+    se = ((hb0 + k) << 5) + 1;
+  }
+  return gary_first<G>((uint32_t)(sb - lo), (uint32_t)(se - lo), gl, gbase, direct);
+}
+
 // Cooperative membership search of up to G keys at once: lane l < nk holds a
 // key; A[0..n) is sorted and strictly increasing (global memory).  The k =
 // G / nk lanes assigned to one key probe k evenly spaced points per round, so
@@ -248,6 +279,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const RT* __restrict__ R = (const RT*)a.g.R;
+  const RT* __restrict__ HR = (const RT*)a.g.HR;
   const uint64_t lt_mask = (gl == 0) ? 0ull : ((~0ull) >> (64 - gl));  // group lanes below gl
   const uint64_t P16 = a.P16, Q16 = a.Q16;
   const uint64_t cdel = (uint64_t)kC16 - Q16;  // common minus far, mod 2^64
@@ -431,7 +463,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           if (S == 0) break;
           const uint64_t T = scale_draw(r, S);
           if (WEIGHTED) {
-            jsel = gary_first<G>(0u, d, gl, gbase, [&](uint32_t j) { return (uint64_t)R[lo + j] > T; });
+            jsel = gary_first_heads<G>(R, HR, lo, 0u, d, gl, gbase, [&](uint64_t v, uint32_t) { return v > T; });
           } else {
             jsel = (uint32_t)T;
           }
@@ -684,9 +716,15 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
               Eprev = CW;
             }
             const uint64_t base = cdel * Eprev;
-            jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
-              return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
-            });
+            if constexpr (WEIGHTED) {
+              jsel = gary_first_heads<G>(R, HR, lo, seg_lo, seg_hi, gl, gbase, [&](uint64_t v, uint32_t j) {
+                return Q16 * v + base + ((has_t && j >= pt) ? retw : 0ull) > T;
+              });
+            } else {
+              jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
+                return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
+              });
+            }
           }
         }
         if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
@@ -788,6 +826,7 @@ struct GraphDevG {
   int64_t n;
   uint64_t m;
   const N2V_GLOBAL uint4* NR;
+  const N2V_GLOBAL void* HR;
 };
 struct WalkArgsG {
   GraphDevG g;
@@ -806,6 +845,7 @@ struct WalkArgsG {
   N2V_GLOBAL unsigned long long* steps;
 };
 static_assert(sizeof(WalkArgsG) == sizeof(WalkArgs) && offsetof(WalkArgsG, g.NR) == offsetof(WalkArgs, g.NR) &&
+                  offsetof(WalkArgsG, g.HR) == offsetof(WalkArgs, g.HR) &&
                   offsetof(WalkArgsG, starts) == offsetof(WalkArgs, starts) &&
                   offsetof(WalkArgsG, seed) == offsetof(WalkArgs, seed) && offsetof(WalkArgsG, Y) == offsetof(WalkArgs, Y) &&
                   offsetof(WalkArgsG, path) == offsetof(WalkArgs, path) &&
@@ -822,6 +862,7 @@ __device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
   a.g.n = r.g.n;
   a.g.m = r.g.m;
   a.g.NR = (const uint4*)r.g.NR;
+  a.g.HR = (const void*)r.g.HR;
   a.starts = (const int32_t*)r.starts;
   a.ns = r.ns;
   a.nwalks = r.nwalks;
