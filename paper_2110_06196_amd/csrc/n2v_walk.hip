@@ -25,18 +25,23 @@
 //      set difference N(v) minus N(t) that follows it) and the position pt of
 //      t (return bias), the cumulative sum is
 //        B_j = Q16 R_j + (C16 - Q16) sum_{c in C, c <= j} w_c + (P16 - Q16) w_t [j >= pt]
-//      (mod 2^64; exact because the true B_j < 2^64).  C is built by the cheaper
-//      of two equivalent routes: probe every y in N(t) into N(v) by bisection
-//      (short N(t), long N(v): the typical leaf-to-hub step), or stream N(v)
-//      and test each x against N(t) (kept in LDS when the previous row fit a
-//      ping-pong tile, else bisected in global memory).  The draw is then
-//      located by a ballot over B at the listed positions and a G-ary search
-//      of the segment between two of them.  C is kept in LDS one page at a
-//      time: the first pass counts every common neighbour (so the total is
-//      exact) and stores the first page; later pages are listed only if the
-//      draw lands beyond the stored ones.  A two-pass stream of the biased
-//      weights (block sums, then a scan of one block) remains as a route that
-//      can be forced for testing.
+//      (mod 2^64; exact because the true B_j < 2^64).  C is built by the
+//      cheapest (by a latency estimate) of three equivalent routes: probe
+//      every y in N(t) into N(v) by bisection (short N(t), long N(v): the
+//      typical leaf-to-hub step), stream N(v) and test each x against N(t)
+//      (kept in LDS when the previous row fit a ping-pong tile, else bisected
+//      in global memory), or merge both rows, a window of N(t) at a time in
+//      LDS.  The draw is then located by a ballot over B at the listed
+//      positions and a G-ary search of the segment between two of them.  C is
+//      kept in LDS one page at a time: the first pass counts every common
+//      neighbour (so the total is exact) and stores the first page; later
+//      pages are listed only if the draw lands beyond the stored ones.  A
+//      two-pass stream of the biased weights (block sums, then a scan of one
+//      block) remains as a route that can be forced for testing.
+//
+// Walks are handed to groups (lanes, for k_walk_lane) from a per-stream
+// device counter, a few at a time, so that heavy-tailed walk costs do not
+// leave a launch waiting on its slowest fixed share.
 #include "n2v_device.hpp"
 #include "n2v_internal.hpp"
 
@@ -222,15 +227,6 @@ __device__ __forceinline__ uint32_t gary_first_heads(const RT* __restrict__ V, c
   return gary_first<G>((uint32_t)(sb - lo), (uint32_t)(se - lo), gl, gbase, direct);
 }
 
-// Cooperative membership search of up to G keys at once: lane l < nk holds a
-// key; A[0..n) is sorted and strictly increasing (global memory).  The k =
-// G / nk lanes assigned to one key probe k evenly spaced points per round, so
-// a search takes about log_{k+1}(n) dependent loads instead of log2(n).
-// Returns, in lane l < nk, whether its key is in A and (if so) its index.
-
-// One whole walk (row w of request a) by one group of G lanes; mem is the
-// group's LDS region of group_lds_words(tile, cap, G) words.  FULL adds the
-// approximated step and the forced two-pass route to the exact routes.
 // Splitters of a long sorted row A[0..n) (n >= 4G): the group loads A[l n / G]
 // for its G lanes into LDS (one coalesced round), and every lane can then
 // bisect a key among the splitters in LDS and the key's 1/G slice of A in
@@ -265,6 +261,9 @@ __device__ __forceinline__ uint32_t split_floor(const int32_t* __restrict__ A, u
   return floor_search(A, b, e - b, spl[lo - 1], y, val);
 }
 
+// One whole walk (row w of request a) by one group of G lanes; mem is the
+// group's LDS region of group_lds_words(tile, cap, G) words.  FULL adds the
+// approximated step and the forced two-pass route to the exact routes.
 template <int G, bool WEIGHTED, typename RT, bool FULL>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
                                            int mode_knob) {
