@@ -175,7 +175,12 @@ int n2v_ef_rank(n2v_graph g, const uint64_t* d_x, uint64_t count, uint64_t* d_ou
  * All caller-owned.  Arguments are validated synchronously, then the work is
  * enqueued on hip_stream; the outputs are valid once the stream has been
  * synchronised.  A start outside [0, n_nodes) yields a row of -1 with length 0
- * (not an error).  n_starts == 0 is a no-op.  Reentrant across streams.
+ * (not an error).  n_starts == 0 is a no-op.  Reentrant across streams and
+ * threads.  The kernels hand walks out from a device counter of hip_stream:
+ * the first call on a stream takes 8 bytes for it from a library-owned device
+ * slab (hipMalloc of 4 KB per 512 streams, kept until the process ends); a
+ * stream under graph capture gets no counter and the walks are split in fixed
+ * shares instead (same output).
  * Errors: INVALID_ARG, BAD_HANDLE, OVERFLOW (node2vec), HIP.
  * ------------------------------------------------------------------------- */
 int n2v_walks_first_order(n2v_graph g, const int32_t* d_starts, uint64_t n_starts,
