@@ -303,6 +303,7 @@ void free_record(GraphRec* gr) {
   if (gr->dev.R) hipFree(const_cast<void*>(gr->dev.R));
   if (gr->dev.NR) hipFree(const_cast<uint4*>(gr->dev.NR));
   if (gr->dev.HR) hipFree(const_cast<void*>(gr->dev.HR));
+  if (gr->dev.HD) hipFree(const_cast<int32_t*>(gr->dev.HD));
   if (gr->neg_guide) hipFree(gr->neg_guide);
   if (gr->ef_mem) hipFree(gr->ef_mem);
   delete gr;
@@ -333,6 +334,24 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
   gr->dev.D = d_dst;
   gr->dev.W = d_weights;
   rc = build_prefix(gr, d_offsets, d_weights, st, true);
+  if (rc == N2V_OK && gr->max_degree > kHeadsMinDegree) {
+    const uint64_t hbytes = ((n_entries + 31) >> 5) * sizeof(int32_t);
+    int32_t* HD = nullptr;
+    hipError_t e = hipMalloc((void**)&HD, (size_t)hbytes);
+    if (e != hipSuccess) {
+      rc = fail(N2V_ERR_NOMEM, "hipMalloc destination heads: %s", hipGetErrorString(e));
+    } else {
+      e = launch_dest_heads(d_dst, n_entries, HD, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        hipFree(HD);
+        rc = hip_fail(e, "destination heads");
+      } else {
+        gr->dev.HD = HD;
+        gr->owned_bytes += hbytes;
+      }
+    }
+  }
   if (rc != N2V_OK) {
     free_record(gr);
     return rc;

@@ -28,7 +28,15 @@ struct GraphDev {
   // searches the row's heads, which are contiguous, then one 32-entry block of
   // R.  Null otherwise.
   const void* HR = nullptr;
+  // CSR graphs with a row longer than kHeadsMinDegree: the destination at
+  // every 32nd entry, HD[i] = D[32 i] (ceil(m / 32) entries).  A bisection over
+  // a long splitter slice of a row searches the slice's heads, then one
+  // 32-entry block of D.  Null otherwise.
+  const int32_t* HD = nullptr;
 };
+
+// Rows at which a 64-way splitter slice exceeds 1024 entries.
+constexpr uint64_t kHeadsMinDegree = 64ull * 1024;
 
 // Which kernel family serves a request.
 enum class Path : int {
@@ -133,6 +141,8 @@ hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D,
 hipError_t launch_node_records(const uint64_t* O, int64_t n, const uint32_t* R, uint4* NR, hipStream_t st);
 // HR[i] = R[32 i] for i < ceil(m / 32); R of r_bytes (4 or 8) per entry.
 hipError_t launch_prefix_heads(const void* R, uint32_t r_bytes, uint64_t m, void* HR, hipStream_t st);
+// HD[i] = D[32 i] for i < ceil(m / 32).
+hipError_t launch_dest_heads(const int32_t* D, uint64_t m, int32_t* HD, hipStream_t st);
 hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,
                              uint32_t r_bytes, hipStream_t st);
 

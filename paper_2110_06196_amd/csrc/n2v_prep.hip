@@ -126,6 +126,15 @@ hipError_t launch_prefix_heads(const void* R, uint32_t r_bytes, uint64_t m, void
   return hipGetLastError();
 }
 
+hipError_t launch_dest_heads(const int32_t* D, uint64_t m, int32_t* HD, hipStream_t st) {
+  const uint64_t nh = (m + 31) >> 5;
+  if (nh == 0) return hipSuccess;
+  uint64_t blocks = (nh + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  hipLaunchKernelGGL(k_prefix_heads<int32_t>, dim3((unsigned)blocks), dim3(256), 0, st, D, nh, HD);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate_stats(const uint64_t* O, int64_t n, const int32_t* D, uint64_t m,
                                  const uint32_t* W, uint64_t* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_validate_stats, dim3(prep_blocks(n)), dim3(256), 0, st, O, n, D, m, W,

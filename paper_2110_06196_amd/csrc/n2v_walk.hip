@@ -238,14 +238,17 @@ __device__ __forceinline__ void load_splitters(const int32_t* __restrict__ A, ui
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Floor search of y in A[0, n) (n >= G) that starts from the slice between
-// the splitters around y: the splitter below y is the slice's first entry, so
-// its value comes from LDS.  Returns the position and its value as
-// floor_search does (value != y when y is not in A).
+// Floor search of y in the row D[P, P + n) (n >= G) that starts from the
+// slice between the splitters around y: the splitter below y is the slice's
+// first entry, so its value comes from LDS.  A slice longer than 1024 entries
+// continues through its heads HD[i] = D[32 i] (contiguous, a few lines) and
+// then one 32-entry block of D, instead of bisecting D itself (a line per
+// probe).  Returns the position in the row and its value as floor_search does
+// (value != y when y is not in the row).
 template <int G>
-__device__ __forceinline__ uint32_t split_floor(const int32_t* __restrict__ A, uint32_t n, const int32_t* spl,
-                                                int32_t y, int32_t& val) {
-  // first splitter index l with spl[l] > y (spl[0] = A[0]); 0 -> y < A[0]
+__device__ __forceinline__ uint32_t split_floor(const int32_t* __restrict__ D, const int32_t* __restrict__ HD,
+                                                uint64_t P, uint32_t n, const int32_t* spl, int32_t y, int32_t& val) {
+  // first splitter index l with spl[l] > y (spl[0] = D[P]); 0 -> y < D[P]
   int lo = 0, hi = G;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
@@ -258,13 +261,25 @@ __device__ __forceinline__ uint32_t split_floor(const int32_t* __restrict__ A, u
   }
   const uint32_t b = (uint32_t)(((uint64_t)(lo - 1) * n) / G);
   const uint32_t e = lo < G ? (uint32_t)(((uint64_t)lo * n) / G) : n;
-  return floor_search(A, b, e - b, spl[lo - 1], y, val);
+  const int32_t vb = spl[lo - 1];
+  if (HD == nullptr || e - b <= 1024u) return floor_search(D + P, b, e - b, vb, y, val);
+  const uint64_t s0 = P + b, s1 = P + e;                    // D[s0] = vb <= y
+  const uint64_t hb0 = (s0 + 31) >> 5, hb1 = (s1 - 1) >> 5;  // heads inside the slice (at least 32)
+  const int32_t h0 = HD[hb0];
+  if (h0 > y) return b + floor_search(D + s0, 0u, (uint32_t)((hb0 << 5) - s0), vb, y, val);
+  int32_t hv;
+  const uint32_t i = floor_search(HD + hb0, 0u, (uint32_t)(hb1 - hb0 + 1), h0, y, hv);
+  const uint64_t B = (hb0 + i) << 5;
+  const uint32_t len = (uint32_t)(s1 - B < 32u ? s1 - B : 32u);
+  return (uint32_t)(B - P) + floor_search(D + B, 0u, len, hv, y, val);
 }
 
 // One whole walk (row w of request a) by one group of G lanes; mem is the
 // group's LDS region of group_lds_words(tile, cap, G) words.  FULL adds the
-// approximated step and the forced two-pass route to the exact routes.
-template <int G, bool WEIGHTED, typename RT, bool FULL>
+// approximated step and the forced two-pass route to the exact routes; HEADS
+// the head search of long splitter slices (graphs with rows longer than
+// kHeadsMinDegree, which alone carry destination heads).
+template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS = false>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
                                            int mode_knob) {
   const int lane = threadIdx.x & 63;
@@ -279,6 +294,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   const int32_t* __restrict__ D = a.g.D;
   const RT* __restrict__ R = (const RT*)a.g.R;
   const RT* __restrict__ HR = (const RT*)a.g.HR;
+  const int32_t* __restrict__ HD = HEADS ? a.g.HD : nullptr;
   const uint64_t lt_mask = (gl == 0) ? 0ull : ((~0ull) >> (64 - gl));  // group lanes below gl
   const uint64_t P16 = a.P16, Q16 = a.Q16;
   const uint64_t cdel = (uint64_t)kC16 - Q16;  // common minus far, mod 2^64
@@ -407,7 +423,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             bool common;
             if (split_t) {
               int32_t val;
-              split_floor<G>(D + tlo, td, win, x, val);
+              split_floor<G>(D, HD, tlo, td, win, x, val);
               common = val == x;
             } else {
               common = member(x);
@@ -535,7 +551,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   bool hit = false;
                   if (act) {
                     int32_t val;
-                    pos = split ? split_floor<G>(D + lo, d, win, y, val) : floor_search(D + lo, 0u, d, D[lo], y, val);
+                    pos = split ? split_floor<G>(D, HD, lo, d, win, y, val) : floor_search(D + lo, 0u, d, D[lo], y, val);
                     hit = val == y;
                   }
                   const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
@@ -634,7 +650,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                       in_t = false;
                       if (act && !isret) {
                         int32_t val;
-                        split_floor<G>(D + tlo, td, win, x, val);
+                        split_floor<G>(D, HD, tlo, td, win, x, val);
                         in_t = val == x;
                       }
                     } else {
@@ -760,7 +776,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   }
 }
 
-template <int G, bool WEIGHTED, typename RT, bool FULL>
+template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS>
 __global__ __launch_bounds__(256, G == 64 ? 8 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
                                                                                    unsigned long long* ctr, uint32_t chunk) {
   extern __shared__ int32_t lds[];
@@ -784,7 +800,7 @@ __global__ __launch_bounds__(256, G == 64 ? 8 : 1) void k_walk_n2v(WalkArgs a, i
       }
     }
     if (w >= a.nwalks) break;
-    group_walk<G, WEIGHTED, RT, FULL>(a, w, mem, tile, cap, mode_knob);
+    group_walk<G, WEIGHTED, RT, FULL, HEADS>(a, w, mem, tile, cap, mode_knob);
     w += ctr ? 1 : ngroups;
   }
 }
@@ -826,6 +842,7 @@ struct GraphDevG {
   uint64_t m;
   const N2V_GLOBAL uint4* NR;
   const N2V_GLOBAL void* HR;
+  const N2V_GLOBAL int32_t* HD;
 };
 struct WalkArgsG {
   GraphDevG g;
@@ -845,6 +862,7 @@ struct WalkArgsG {
 };
 static_assert(sizeof(WalkArgsG) == sizeof(WalkArgs) && offsetof(WalkArgsG, g.NR) == offsetof(WalkArgs, g.NR) &&
                   offsetof(WalkArgsG, g.HR) == offsetof(WalkArgs, g.HR) &&
+                  offsetof(WalkArgsG, g.HD) == offsetof(WalkArgs, g.HD) &&
                   offsetof(WalkArgsG, starts) == offsetof(WalkArgs, starts) &&
                   offsetof(WalkArgsG, seed) == offsetof(WalkArgs, seed) && offsetof(WalkArgsG, Y) == offsetof(WalkArgs, Y) &&
                   offsetof(WalkArgsG, path) == offsetof(WalkArgs, path) &&
@@ -862,6 +880,7 @@ __device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
   a.g.m = r.g.m;
   a.g.NR = (const uint4*)r.g.NR;
   a.g.HR = (const void*)r.g.HR;
+  a.g.HD = (const int32_t*)r.g.HD;
   a.starts = (const int32_t*)r.starts;
   a.ns = r.ns;
   a.nwalks = r.nwalks;
@@ -990,7 +1009,10 @@ hipError_t go_lane(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, h
 template <int G, bool WEIGHTED, typename RT>
 hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   const bool full = a.k_approx != 0 || cfg.mode == kModeTwoPass;
-  auto k = full ? k_walk_n2v<G, WEIGHTED, RT, true> : k_walk_n2v<G, WEIGHTED, RT, false>;
+  // 64-lane groups on graphs with destination heads take the head search
+  const bool heads = G == 64 && a.g.HD != nullptr;
+  auto k = full ? (heads ? k_walk_n2v<G, WEIGHTED, RT, true, G == 64> : k_walk_n2v<G, WEIGHTED, RT, true, false>)
+                : (heads ? k_walk_n2v<G, WEIGHTED, RT, false, G == 64> : k_walk_n2v<G, WEIGHTED, RT, false, false>);
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);

@@ -152,6 +152,36 @@ def test_hub_rows_all_routes():
     _tuning_sweep(O, D, W, rows, 24, cases, grid)
 
 
+def test_giant_hub_rows_head_search():
+    """Hubs adjacent to ~80% of 150,000 nodes: a 64-splitter slice of such a row
+    holds ~1900 entries, so bisections go through the destination heads
+    (every 32nd entry) and one 32-entry block.  Auto, probe and stream routes."""
+    rng = np.random.default_rng(77)
+    n = 150000
+    hubs = rng.choice(n, size=6, replace=False)
+    src, dst = [], []
+    for h in hubs:
+        nb = np.nonzero(rng.random(n) < 0.8)[0]
+        src.append(np.full(nb.size, h))
+        dst.append(nb)
+    src.append(rng.integers(0, n, 300000))
+    dst.append(rng.integers(0, n, 300000))
+    src, dst = np.concatenate(src), np.concatenate(dst)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    O, D, W = synth.csr_from_edges(n, src, dst, rng.integers(1, 1001, src.size), symmetric=True)
+    deg = (O[1:] - O[:-1]).astype(np.int64)
+    assert deg.max() > 1024 * 64  # splitter slices above 1024 entries
+    starts = np.concatenate([hubs, rng.integers(0, n, 400)])
+    g, keep_t = upload(O, D, W)
+    for route in (0, 2, 3):
+        n2v.n2v_set_tuning(route=route)
+        for p, q in ((0.25, 4.0), (1.0, 2.0)):
+            check(O, D, W, starts, 1, 8, NV, p, q, seed=5, g=g)
+    n2v.n2v_set_tuning(reset=True)
+    n2v.n2v_graph_release(g)
+
+
 def test_ba_10k_full():
     """Barabasi-Albert, 10,000 nodes, m = 5, node2vec p = 2, q = 0.5, one walk of
     80 slots per node, seed 42: every walk."""
