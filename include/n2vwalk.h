@@ -77,6 +77,8 @@ typedef struct {
   uint64_t device_bytes;   /* library-owned device memory held by this graph */
   uint32_t storage;        /* N2V_STORAGE_CSR or N2V_STORAGE_EF */
   uint32_t ef_quantum;     /* quantum of the Elias-Fano indexes (0 for CSR) */
+  uint64_t pair_lists;     /* edges whose common-neighbour list is stored (see n2v_graph_upload) */
+  uint64_t pair_entries;   /* entries of those lists (16 bytes each) */
 } n2v_graph_info_t;
 
 enum { N2V_STORAGE_CSR = 0, N2V_STORAGE_EF = 1 };
@@ -99,6 +101,8 @@ enum {
   N2V_ROUTE_MERGE = 4     /* merge the two sorted rows, a window of N(t) at a time in LDS */
 };
 
+enum { N2V_UPLOAD_NO_PAIR_LISTS = 1u };
+
 enum {
   N2V_TUNE_GENERIC_ONLY = 1u  /* route every step through the G-lanes-per-walker kernel
                                  (no first-order / 1/q == 1 lane-per-walker specialisations) */
@@ -111,10 +115,19 @@ enum {
  * d_dst[offsets[v] .. offsets[v+1]) strictly increasing (the sorted neighbour
  * set of the paper's CSR store, Methods "Succinct data structures").
  * d_weights: device uint32[n_entries], or NULL for an unweighted graph
- * (every weight 1).  flags must be 0.
+ * (every weight 1).  flags: 0, or N2V_UPLOAD_NO_PAIR_LISTS.
  * The three arrays are BORROWED: the caller keeps them alive and unchanged
  * until n2v_graph_release.  Derived arrays (per-row inclusive weight prefix,
  * statistics) are owned by the library.
+ * For weighted graphs with row sums below 2^32 and at most 2^28 entries the
+ * upload also stores, for every edge t -> v, the list a second-order step
+ * from v after t builds: the positions in N(v) of the common neighbours
+ * (x in N(t), x != t) with the prefix of their weights, and the position of
+ * t in N(v).  All lists are kept when they fit min(32 GiB, 256 bytes per
+ * graph entry), else the ones with the most saved work per stored entry;
+ * n2v_graph_info reports them.  They change no walk, only how fast its steps
+ * run, and cost upload time (about 1 s per 2e7 entries of a power-law graph).
+ * N2V_UPLOAD_NO_PAIR_LISTS skips them.
  * Synchronous: validates on the device, builds the derived arrays on
  * hip_stream and waits for it.  Errors: INVALID_ARG, UNSORTED, NOMEM, HIP.
  * ------------------------------------------------------------------------- */

@@ -24,6 +24,7 @@ N2V_ERR_NOMEM, N2V_ERR_HIP, N2V_ERR_BAD_HANDLE, N2V_ERR_REJECTED = -4, -5, -6, -
 N2V_STORAGE_CSR, N2V_STORAGE_EF = 0, 1
 N2V_FIRST_ORDER, N2V_NODE2VEC = 0, 1
 N2V_TUNE_GENERIC_ONLY = 1
+N2V_UPLOAD_NO_PAIR_LISTS = 1
 N2V_ROUTE_AUTO, N2V_ROUTE_TWO_PASS, N2V_ROUTE_PROBE, N2V_ROUTE_STREAM, N2V_ROUTE_MERGE = 0, 1, 2, 3, 4
 N2V_BATCH_AUTOTUNE = 1
 
@@ -44,7 +45,8 @@ class GraphInfo(ctypes.Structure):
                 ("max_degree", ctypes.c_uint64), ("max_row_wsum", ctypes.c_uint64),
                 ("sum_deg_sq", ctypes.c_uint64), ("weighted", ctypes.c_uint32),
                 ("prefix_bytes", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
-                ("storage", ctypes.c_uint32), ("ef_quantum", ctypes.c_uint32)]
+                ("storage", ctypes.c_uint32), ("ef_quantum", ctypes.c_uint32),
+                ("pair_lists", ctypes.c_uint64), ("pair_entries", ctypes.c_uint64)]
 
 
 class EFInfo(ctypes.Structure):
@@ -163,10 +165,11 @@ def _dev(t, dtype, name):
 # ---------------------------------------------------------------------------
 # Graphs
 # ---------------------------------------------------------------------------
-def n2v_graph_upload(offsets, dst, weights=None, stream=None) -> int:
+def n2v_graph_upload(offsets, dst, weights=None, stream=None, flags: int = 0) -> int:
     """Register a CSR graph held in device tensors (uint64 / int64 offsets,
     int32 destinations, optional int32/uint32 weights viewed as uint32).
-    The tensors are borrowed: keep them alive until n2v_graph_release."""
+    The tensors are borrowed: keep them alive until n2v_graph_release.
+    flags: 0 or N2V_UPLOAD_NO_PAIR_LISTS."""
     if offsets.dtype == torch.int64:
         offsets = offsets.view(torch.uint64) if hasattr(torch, "uint64") else offsets
     _dev(dst, torch.int32, "dst")
@@ -174,7 +177,7 @@ def n2v_graph_upload(offsets, dst, weights=None, stream=None) -> int:
         raise N2VError(N2V_ERR_INVALID_ARG, "weights must be uint32 (or int32 bit pattern)")
     h = ctypes.c_uint64(0)
     _check(lib().n2v_graph_upload(_ptr(offsets), offsets.numel() - 1, _ptr(dst), dst.numel(),
-                                  _ptr(weights), 0, _stream(stream), ctypes.byref(h)))
+                                  _ptr(weights), flags, _stream(stream), ctypes.byref(h)))
     # The library reads these arrays until release: hold them so that the
     # caching allocator cannot hand their memory to another tensor meanwhile.
     _borrowed[h.value] = (offsets, dst, weights)

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libn2vwalk.so")
 
-SOURCES = ["n2v_api.cpp", "n2v_serve.cpp", "n2v_prep.hip", "n2v_walk.hip", "n2v_corpus.hip", "n2v_ef.hip"]
+SOURCES = ["n2v_api.cpp", "n2v_serve.cpp", "n2v_prep.hip", "n2v_walk.hip", "n2v_corpus.hip", "n2v_ef.hip",
+           "n2v_pairs.hip"]
 
 # memory-system probes for the benchmark's gather roofline (not the walk library)
 MEMBENCH_SOURCES = ["n2v_membench.hip"]

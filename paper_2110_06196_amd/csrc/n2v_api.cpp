@@ -8,9 +8,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "n2v_internal.hpp"
 #include "n2v_runtime.hpp"
@@ -292,6 +295,116 @@ int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weig
   return N2V_OK;
 }
 
+// Stored common-neighbour lists of edges (n2v_pairs.hip), for weighted graphs
+// with 32-bit prefixes and at most kListMaxEntries entries, when measuring
+// them takes at most kListWorkCap bisection reads.  Every edge's list is kept
+// when all fit the budget of min(kListBudgetMax, 256 m) bytes (16 B per entry,
+// so 16 entries per graph entry); otherwise the edges with the most merge work
+// per stored entry, (d_t + d_v) / (entries + 4), are kept until it is full.
+constexpr uint64_t kListMaxEntries = 1ull << 28;
+constexpr uint64_t kListWorkCap = 1ull << 37;
+constexpr uint64_t kListBudgetMax = 32ull << 30;
+
+// Device temporaries of one build, freed when it ends.
+struct DeviceTemps {
+  std::vector<void*> p;
+  ~DeviceTemps() {
+    for (void* q : p) (void)hipFree(q);
+  }
+  template <typename T>
+  hipError_t alloc(T** out, size_t count) {
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, count ? count * sizeof(T) : 1);
+    if (e == hipSuccess) p.push_back(q);
+    *out = (T*)q;
+    return e;
+  }
+};
+
+void free_edge_lists(GraphDev& g) {
+  if (g.pair_info) (void)hipFree(const_cast<uint4*>(g.pair_info));
+  if (g.pair_ent) (void)hipFree(const_cast<uint4*>(g.pair_ent));
+  g.pair_info = nullptr;
+  g.pair_ent = nullptr;
+}
+
+int build_edge_lists(GraphRec* gr, hipStream_t st) {
+  GraphDev& g = gr->dev;
+  const uint64_t n = gr->n_nodes, m = gr->n_entries;
+  if (!g.R || g.r_bytes != 4 || m == 0 || m > kListMaxEntries) return N2V_OK;
+  DeviceTemps tmp;
+  auto hipf = [&](hipError_t e, const char* what) -> int {
+    free_edge_lists(g);
+    return e == hipErrorOutOfMemory ? fail(N2V_ERR_NOMEM, "edge lists: %s", what) : hip_fail(e, what);
+  };
+  std::vector<uint64_t> hO(n + 1);
+  std::vector<int32_t> hD(m);
+  hipError_t e = hipMemcpy(hO.data(), g.O, (n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(hD.data(), g.D, m * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hipf(e, "edge lists: graph");
+  auto deg = [&](uint64_t u) { return hO[u + 1] - hO[u]; };
+  auto bits = [](uint64_t x) { return (uint64_t)(64 - __builtin_clzll(x | 1)); };
+  std::vector<int32_t> src(m);  // source row of every entry
+  uint64_t work = 0;
+  for (uint64_t t = 0; t < n; ++t)
+    for (uint64_t k = hO[t]; k < hO[t + 1]; ++k) {
+      src[k] = (int32_t)t;
+      const uint64_t dt = deg(t), dv = deg((uint64_t)hD[k]);
+      work += std::min(dt, dv) * bits(std::max(dt, dv));
+    }
+  if (work > kListWorkCap) return N2V_OK;
+  uint32_t *d_cnt, *d_pt;
+  int32_t* d_src;
+  if ((e = tmp.alloc(&d_cnt, m)) != hipSuccess || (e = tmp.alloc(&d_pt, m)) != hipSuccess ||
+      (e = tmp.alloc(&d_src, m)) != hipSuccess)
+    return hipf(e, "allocation");
+  if ((e = hipMemcpy(d_src, src.data(), m * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = launch_edge_lists_measure(g.O, g.D, d_src, m, d_cnt, d_pt, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hipf(e, "edge list measure");
+  std::vector<uint32_t> cnt(m), pt(m);
+  if ((e = hipMemcpy(cnt.data(), d_cnt, m * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(pt.data(), d_pt, m * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hipf(e, "edge list measure");
+  const uint64_t budget = std::min<uint64_t>(kListBudgetMax, 256ull * m) / sizeof(uint4);
+  uint64_t all = 0;
+  for (uint64_t k = 0; k < m; ++k) all += cnt[k];
+  std::vector<uint4> info(m, make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu));
+  uint64_t total = 0, kept = 0;
+  auto keep = [&](uint64_t k) {
+    info[k] = make_uint4((uint32_t)total, (uint32_t)(total >> 32), cnt[k], pt[k]);
+    total += cnt[k];
+    ++kept;
+  };
+  if (all <= budget) {
+    for (uint64_t k = 0; k < m; ++k) keep(k);
+  } else {
+    std::vector<uint32_t> order(m);
+    std::iota(order.begin(), order.end(), 0u);
+    auto gain = [&](uint32_t k) { return (double)(deg((uint64_t)src[k]) + deg((uint64_t)hD[k])) / (cnt[k] + 4.0); };
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+      const double ga = gain(a), gb = gain(b);
+      return ga > gb || (ga == gb && a < b);
+    });
+    for (uint32_t k : order)
+      if (total + cnt[k] <= budget) keep(k);
+  }
+  uint4* d_info = nullptr;
+  uint4* d_ent = nullptr;
+  if ((e = hipMalloc((void**)&d_info, m * sizeof(uint4))) != hipSuccess) return hipf(e, "allocation");
+  g.pair_info = d_info;
+  if ((e = hipMalloc((void**)&d_ent, (total ? total : 1) * sizeof(uint4))) != hipSuccess) return hipf(e, "allocation");
+  g.pair_ent = d_ent;
+  if ((e = hipMemcpy(d_info, info.data(), m * sizeof(uint4), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = launch_edge_lists_fill(g.O, g.D, d_src, m, (const uint32_t*)g.R, d_info, d_ent, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hipf(e, "edge list fill");
+  gr->owned_bytes += m * sizeof(uint4) + total * sizeof(uint4);
+  gr->pair_lists = kept;
+  gr->pair_entries = total;
+  return N2V_OK;
+}
+
 n2v_graph register_graph(GraphRec* gr) {
   std::lock_guard<std::mutex> lk(g_mu);
   gr->handle = g_next_graph++;
@@ -304,6 +417,7 @@ void free_record(GraphRec* gr) {
   if (gr->dev.NR) hipFree(const_cast<uint4*>(gr->dev.NR));
   if (gr->dev.HR) hipFree(const_cast<void*>(gr->dev.HR));
   if (gr->dev.HD) hipFree(const_cast<int32_t*>(gr->dev.HD));
+  free_edge_lists(gr->dev);
   if (gr->neg_guide) hipFree(gr->neg_guide);
   if (gr->ef_mem) hipFree(gr->ef_mem);
   delete gr;
@@ -319,7 +433,8 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
                      void* hip_stream, n2v_graph* out) {
   if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
   *out = 0;
-  if (flags != 0) return fail(N2V_ERR_INVALID_ARG, "flags must be 0");
+  if ((flags & ~(uint32_t)N2V_UPLOAD_NO_PAIR_LISTS) != 0)
+    return fail(N2V_ERR_INVALID_ARG, "flags: unknown bits 0x%x", flags);
   int rc = check_csr_args(d_offsets, n_nodes, d_dst, n_entries);
   if (rc != N2V_OK) return rc;
   DevInfo di;
@@ -352,6 +467,7 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
       }
     }
   }
+  if (rc == N2V_OK && !(flags & N2V_UPLOAD_NO_PAIR_LISTS)) rc = build_edge_lists(gr, st);
   if (rc != N2V_OK) {
     free_record(gr);
     return rc;
@@ -479,6 +595,8 @@ int n2v_graph_info(n2v_graph g, n2v_graph_info_t* out) {
   out->device_bytes = gr->owned_bytes;
   out->storage = gr->storage;
   out->ef_quantum = gr->ef_quantum;
+  out->pair_lists = gr->pair_lists;
+  out->pair_entries = gr->pair_entries;
   return N2V_OK;
 }
 

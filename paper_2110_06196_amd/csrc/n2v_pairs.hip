@@ -1,0 +1,145 @@
+// Common-neighbour lists of edges, built once per graph.
+//
+// A second-order step from v after t needs the positions j in N(v) whose
+// candidate is a common neighbour (x in N(t), x != t), the prefix of their
+// weights and the position of t in N(v) (Methods, "Efficient sampling for
+// Node2Vec RWs": the in-out bias is 1 exactly on N(t), Eq. 3).  Building that
+// list (a merge or a probe of two rows) dominates the step when the rows are
+// long, and walks cross the same edges again and again.  The graph is
+// immutable, so the list of an edge t -> v is a pure function of the graph:
+// these kernels store it, indexed by the edge's position e in the CSR
+// (v = D[e], e in t's row), and the walk kernels read it instead of
+// rebuilding it.  Each entry is {R_v[j], inclusive prefix of the listed
+// weights, j, 0}: exactly the values the list routes compute, so walks stay
+// bit-identical.
+//
+// Passes (one wavefront per edge; the lanes split the shorter of N(t) and
+// N(v) and bisect the other; walking N(t) yields the positions in N(v) in
+// increasing order too, so a ballot keeps the entries sorted):
+//   k_edge_lists_measure  per edge: number of common neighbours, position of t in N(v)
+//   k_edge_lists_fill     per kept edge: the entries, in increasing j
+// The host picks the edges to keep.
+#include "n2v_device.hpp"
+#include "n2v_internal.hpp"
+
+namespace n2v {
+
+namespace {
+
+__device__ __forceinline__ int64_t wave_index() { return ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; }
+__device__ __forceinline__ int64_t wave_count() { return ((int64_t)gridDim.x * blockDim.x) >> 6; }
+
+// position of x in A[0, n) (n >= 1), or ~0
+__device__ __forceinline__ uint32_t find_in_row(const int32_t* __restrict__ A, uint32_t n, int32_t x) {
+  int32_t val;
+  const uint32_t p = floor_search(A, 0u, n, A[0], x, val);
+  return val == x ? p : 0xFFFFFFFFu;
+}
+
+// The two rows of edge e = (t -> v).
+struct EdgeRows {
+  uint64_t lot, lov;
+  uint32_t dt, dv;
+  int32_t t;
+};
+
+// Candidate i of the shorter row of an edge, searched in the longer one:
+// whether it is a listed common neighbour, and its position p in N(v).
+__device__ __forceinline__ bool chunk_hit(const int32_t* __restrict__ D, const EdgeRows& r, uint32_t i, uint32_t* p) {
+  if (r.dt <= r.dv) {  // candidates from N(t), positions by bisection in N(v)
+    if (i >= r.dt) return false;
+    const int32_t x = D[r.lot + i];
+    if (x == r.t) return false;
+    *p = find_in_row(D + r.lov, r.dv, x);
+    return *p != 0xFFFFFFFFu;
+  }
+  if (i >= r.dv) return false;  // candidates from N(v), membership by bisection in N(t)
+  const int32_t x = D[r.lov + i];
+  *p = i;
+  return x != r.t && find_in_row(D + r.lot, r.dt, x) != 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ EdgeRows edge_rows(const uint64_t* __restrict__ O, const int32_t* __restrict__ D,
+                                              const int32_t* __restrict__ src, uint64_t e) {
+  EdgeRows r;
+  r.t = src[e];
+  const int32_t v = D[e];
+  r.lot = O[r.t];
+  r.dt = (uint32_t)(O[r.t + 1] - r.lot);
+  r.lov = O[v];
+  r.dv = (uint32_t)(O[v + 1] - r.lov);
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_edge_lists_measure(const uint64_t* __restrict__ O,
+                                                            const int32_t* __restrict__ D,
+                                                            const int32_t* __restrict__ src, uint64_t m,
+                                                            uint32_t* __restrict__ cnt,
+                                                            uint32_t* __restrict__ ptpos) {
+  const int lane = threadIdx.x & 63;
+  for (uint64_t e = (uint64_t)wave_index(); e < m; e += (uint64_t)wave_count()) {
+    const EdgeRows r = edge_rows(O, D, src, e);
+    uint32_t c = 0;
+    const uint32_t span = r.dt <= r.dv ? r.dt : r.dv;
+    if (r.dv > 0) {
+      for (uint32_t c0 = 0; c0 < span; c0 += 64) {
+        uint32_t p;
+        c += (uint32_t)__popcll(__ballot(chunk_hit(D, r, c0 + lane, &p)));
+      }
+    }
+    if (lane == 0) {
+      cnt[e] = c;
+      ptpos[e] = r.dv > 0 ? find_in_row(D + r.lov, r.dv, r.t) : 0xFFFFFFFFu;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_edge_lists_fill(const uint64_t* __restrict__ O, const int32_t* __restrict__ D,
+                                                         const int32_t* __restrict__ src, uint64_t m,
+                                                         const uint32_t* __restrict__ R,
+                                                         const uint4* __restrict__ info, uint4* __restrict__ ent) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (uint64_t e = (uint64_t)wave_index(); e < m; e += (uint64_t)wave_count()) {
+    const uint4 inf = info[e];
+    if ((inf.x & inf.y) == 0xFFFFFFFFu || inf.z == 0) continue;  // not kept, or empty
+    const uint64_t off = (uint64_t)inf.x | ((uint64_t)inf.y << 32);
+    const EdgeRows r = edge_rows(O, D, src, e);
+    const uint32_t span = r.dt <= r.dv ? r.dt : r.dv;
+    uint64_t k = 0;
+    uint32_t E = 0;  // listed weight so far (part of the row sum, which fits 32 bits)
+    for (uint32_t c0 = 0; c0 < span; c0 += 64) {
+      uint32_t p = 0;
+      const bool hit = chunk_hit(D, r, c0 + lane, &p);
+      const uint32_t rv = hit ? R[r.lov + p] : 0u;
+      const uint32_t w = hit ? (p ? rv - R[r.lov + p - 1] : rv) : 0u;
+      const uint32_t incl = wave_incl_scan_u32(w);
+      const uint64_t mk = __ballot(hit);
+      if (hit) ent[off + k + (uint64_t)__popcll(mk & lt)] = make_uint4(rv, E + incl, p, 0u);
+      k += (uint64_t)__popcll(mk);
+      E += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    }
+  }
+}
+
+unsigned edge_blocks(uint64_t edges) {
+  uint64_t b = (edges + 3) / 4;
+  if (b > 256 * 64) b = 256 * 64;
+  return (unsigned)(b ? b : 1);
+}
+
+}  // namespace
+
+hipError_t launch_edge_lists_measure(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m, uint32_t* cnt,
+                                     uint32_t* ptpos, hipStream_t st) {
+  hipLaunchKernelGGL(k_edge_lists_measure, dim3(edge_blocks(m)), dim3(256), 0, st, O, D, src, m, cnt, ptpos);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_lists_fill(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m,
+                                  const uint32_t* R, const uint4* info, uint4* ent, hipStream_t st) {
+  hipLaunchKernelGGL(k_edge_lists_fill, dim3(edge_blocks(m)), dim3(256), 0, st, O, D, src, m, R, info, ent);
+  return hipGetLastError();
+}
+
+}  // namespace n2v

@@ -313,6 +313,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
       int32_t v = start, t = -1;
       uint64_t tlo = 0;
       uint32_t td = 0;
+      uint64_t epos = 0;  // position of the edge t -> v in N(t)
       bool t_in_lds = false;
       int32_t* cur = bufA;  // N(t) when staged
       int32_t* nxt = bufB;  // N(v) being staged
@@ -487,6 +488,48 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             staged = true;
           }
         } else {
+          // An edge t -> v whose common-neighbour list is stored (built at
+          // upload, the same list the routes below build): search it.
+          bool cached = false;
+          if constexpr (WEIGHTED && sizeof(RT) == 4) {
+            if (a.g.pair_info != nullptr && mode_knob == kModeAuto) {
+              const uint4 inf = a.g.pair_info[epos];
+              cached = (inf.x & inf.y) != 0xFFFFFFFFu;
+              if (cached) {
+                const uint4* __restrict__ ent = a.g.pair_ent + ((uint64_t)inf.x | ((uint64_t)inf.y << 32));
+                const uint32_t nc = inf.z, ptc = inf.w;
+                const bool has_t = ptc != 0xFFFFFFFFu;
+                const uint64_t CW = nc ? (uint64_t)ent[nc - 1].y : 0ull;
+                const uint64_t retw = has_t ? rdel * Wv(ptc) : 0ull;
+                const uint64_t total = Q16 * S + cdel * CW + retw;
+                if (total == 0) break;
+                const uint64_t T = scale_draw(r, total);
+                // first listed entry with B > T, B = Q16 R_j + cdel E_j + retw [j >= pt]
+                const uint32_t k = gary_first<G>(0u, nc, gl, gbase, [&](uint32_t i) {
+                  const uint4 en = ent[i];
+                  return Q16 * (uint64_t)en.x + cdel * (uint64_t)en.y + ((has_t && en.z >= ptc) ? retw : 0ull) > T;
+                });
+                uint32_t seg_lo = 0, seg_hi = d;
+                uint64_t Eprev = CW;
+                if (k < nc) {
+                  seg_hi = ent[k].z;
+                  Eprev = 0;
+                  if (k > 0) {
+                    const uint4 ep = ent[k - 1];
+                    seg_lo = ep.z + 1;
+                    Eprev = ep.y;
+                  }
+                } else if (nc > 0) {
+                  seg_lo = ent[nc - 1].z + 1;
+                }
+                const uint64_t base = cdel * Eprev;
+                jsel = gary_first_heads<G>(R, HR, lo, seg_lo, seg_hi, gl, gbase, [&](uint64_t v, uint32_t j) {
+                  return Q16 * v + base + ((has_t && j >= ptc) ? retw : 0ull) > T;
+                });
+              }
+            }
+          }
+          if (!cached) {
           int mode = mode_knob;
           if (mode == kModeAuto) {
             // dependent-latency estimate: global load = 100, LDS load = 15
@@ -741,6 +784,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
               });
             }
           }
+          }
         }
         if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
         const int32_t xsel = D[lo + jsel];
@@ -755,6 +799,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         t = v;
         tlo = lo;
         td = d;
+        epos = lo + jsel;
         t_in_lds = staged;
         if (staged) {
           int32_t* tmp = cur;
@@ -843,6 +888,8 @@ struct GraphDevG {
   const N2V_GLOBAL uint4* NR;
   const N2V_GLOBAL void* HR;
   const N2V_GLOBAL int32_t* HD;
+  const N2V_GLOBAL uint4* pair_info;
+  const N2V_GLOBAL uint4* pair_ent;
 };
 struct WalkArgsG {
   GraphDevG g;
@@ -863,6 +910,7 @@ struct WalkArgsG {
 static_assert(sizeof(WalkArgsG) == sizeof(WalkArgs) && offsetof(WalkArgsG, g.NR) == offsetof(WalkArgs, g.NR) &&
                   offsetof(WalkArgsG, g.HR) == offsetof(WalkArgs, g.HR) &&
                   offsetof(WalkArgsG, g.HD) == offsetof(WalkArgs, g.HD) &&
+                  offsetof(WalkArgsG, g.pair_ent) == offsetof(WalkArgs, g.pair_ent) &&
                   offsetof(WalkArgsG, starts) == offsetof(WalkArgs, starts) &&
                   offsetof(WalkArgsG, seed) == offsetof(WalkArgs, seed) && offsetof(WalkArgsG, Y) == offsetof(WalkArgs, Y) &&
                   offsetof(WalkArgsG, path) == offsetof(WalkArgs, path) &&
@@ -881,6 +929,8 @@ __device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
   a.g.NR = (const uint4*)r.g.NR;
   a.g.HR = (const void*)r.g.HR;
   a.g.HD = (const int32_t*)r.g.HD;
+  a.g.pair_info = (const uint4*)r.g.pair_info;
+  a.g.pair_ent = (const uint4*)r.g.pair_ent;
   a.starts = (const int32_t*)r.starts;
   a.ns = r.ns;
   a.nwalks = r.nwalks;

@@ -182,6 +182,30 @@ def test_giant_hub_rows_head_search():
     n2v.n2v_graph_release(g)
 
 
+def test_hub_pair_lists_identical():
+    """Stored common-neighbour lists of hub edges (built at upload) change no
+    walk: a handle with them and one without give the same walks, equal to the
+    oracle, for return / in-out biases on both sides of 1."""
+    O, D, W = synth.chung_lu(20000, 300000, 2.1, 30.0, 8000.0, (1, 1000), seed=21)
+    n = len(O) - 1
+    g1, k1 = upload(O, D, W)
+    Ot, Dt, Wt = k1
+    g0 = n2v.n2v_graph_upload(Ot, Dt, Wt, flags=n2v.N2V_UPLOAD_NO_PAIR_LISTS)
+    i1, i0 = n2v.n2v_graph_info(g1), n2v.n2v_graph_info(g0)
+    assert i1["pair_lists"] > 1000 and i1["pair_entries"] > 0
+    assert i0["pair_lists"] == 0 and i0["pair_entries"] == 0
+    starts = np.arange(n)
+    rows = np.arange(0, n, 29)
+    for p, q in ((0.25, 4.0), (2.0, 0.5), (1.0, 2.0), (4.0, 0.25)):
+        Y1, L1 = run(g1, starts, 1, 40, NV, p, q, seed=8)
+        Y0, L0 = run(g0, starts, 1, 40, NV, p, q, seed=8)
+        assert np.array_equal(Y1, Y0) and np.array_equal(L1, L0), (p, q)
+        Yo, lo = oracle.walks(O, D, W, starts, 1, 40, NV, p, q, 8, 0, rows=rows)
+        assert np.array_equal(Y1[rows], Yo) and np.array_equal(L1[rows], lo), (p, q)
+    n2v.n2v_graph_release(g0)
+    n2v.n2v_graph_release(g1)
+
+
 def test_ba_10k_full():
     """Barabasi-Albert, 10,000 nodes, m = 5, node2vec p = 2, q = 0.5, one walk of
     80 slots per node, seed 42: every walk."""
