@@ -47,6 +47,12 @@ def test_algorithmic_bytes_hand_count():
     deg2 = torch.tensor([1, 3, 40, 50], dtype=torch.int64)
     _, g2 = bench.algorithmic_bytes(torch, Y2, torch.tensor([3], dtype=torch.int32), deg2, "generic")
     assert g2 == c(40) + 32 + (4 * 50 + 4 * 40) + 4 * L(50)
+    # with stored edge lists a later step may read its 16 B list record instead of building the list
+    _, g3 = bench.algorithmic_bytes(torch, Y2, torch.tensor([3], dtype=torch.int32), deg2, "generic", lists=True)
+    assert g3 == c(40) + 32 + 16 + 4 * L(50)
+    _, g4 = bench.algorithmic_bytes(torch, Y, lens, deg, "generic", lists=True)
+    tiny = lambda dt, dv: 32 + min(4 * dt + 4 * dt * L(dv), 4 * dv + 4 * dv * L(dt), 4 * dv + 4 * dt, 16) + 4 * L(dv)
+    assert g4 == c(1) + tiny(1, 3) + tiny(3, 40) + c(40)
 
 
 def test_traffic_needs_matching_source_hash(tmp_path):
