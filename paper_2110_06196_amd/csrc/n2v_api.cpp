@@ -353,27 +353,28 @@ int build_edge_lists(GraphRec* gr, hipStream_t st) {
       work += std::min(dt, dv) * bits(std::max(dt, dv));
     }
   if (work > kListWorkCap) return N2V_OK;
-  uint32_t *d_cnt, *d_pt;
+  uint4* d_meas;
   int32_t* d_src;
-  if ((e = tmp.alloc(&d_cnt, m)) != hipSuccess || (e = tmp.alloc(&d_pt, m)) != hipSuccess ||
-      (e = tmp.alloc(&d_src, m)) != hipSuccess)
+  if ((e = tmp.alloc(&d_meas, m)) != hipSuccess || (e = tmp.alloc(&d_src, m)) != hipSuccess)
     return hipf(e, "allocation");
   if ((e = hipMemcpy(d_src, src.data(), m * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = launch_edge_lists_measure(g.O, g.D, d_src, m, d_cnt, d_pt, st)) != hipSuccess ||
+      (e = launch_edge_lists_measure(g.O, g.D, d_src, m, (const uint32_t*)g.R, d_meas, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return hipf(e, "edge list measure");
-  std::vector<uint32_t> cnt(m), pt(m);
-  if ((e = hipMemcpy(cnt.data(), d_cnt, m * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess ||
-      (e = hipMemcpy(pt.data(), d_pt, m * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+  std::vector<uint4> meas(m);  // {entries, position of t, listed weight, weight of t}
+  if ((e = hipMemcpy(meas.data(), d_meas, m * sizeof(uint4), hipMemcpyDeviceToHost)) != hipSuccess)
     return hipf(e, "edge list measure");
+  // entries are addressed by 32-bit offsets: the budget stays below 2^31 of them
   const uint64_t budget = std::min<uint64_t>(kListBudgetMax, 256ull * m) / sizeof(uint4);
   uint64_t all = 0;
-  for (uint64_t k = 0; k < m; ++k) all += cnt[k];
-  std::vector<uint4> info(m, make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu));
+  for (uint64_t k = 0; k < m; ++k) all += meas[k].x;
+  std::vector<uint4> info(2 * m, make_uint4(0u, 0u, 0u, 0u));
+  for (uint64_t k = 0; k < m; ++k) info[2 * k].x = 0xFFFFFFFFu;
   uint64_t total = 0, kept = 0;
   auto keep = [&](uint64_t k) {
-    info[k] = make_uint4((uint32_t)total, (uint32_t)(total >> 32), cnt[k], pt[k]);
-    total += cnt[k];
+    info[2 * k] = make_uint4((uint32_t)total, meas[k].x, meas[k].y, meas[k].z);
+    info[2 * k + 1] = make_uint4(meas[k].w, 0u, 0u, 0u);
+    total += meas[k].x;
     ++kept;
   };
   if (all <= budget) {
@@ -381,25 +382,25 @@ int build_edge_lists(GraphRec* gr, hipStream_t st) {
   } else {
     std::vector<uint32_t> order(m);
     std::iota(order.begin(), order.end(), 0u);
-    auto gain = [&](uint32_t k) { return (double)(deg((uint64_t)src[k]) + deg((uint64_t)hD[k])) / (cnt[k] + 4.0); };
+    auto gain = [&](uint32_t k) { return (double)(deg((uint64_t)src[k]) + deg((uint64_t)hD[k])) / (meas[k].x + 4.0); };
     std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
       const double ga = gain(a), gb = gain(b);
       return ga > gb || (ga == gb && a < b);
     });
     for (uint32_t k : order)
-      if (total + cnt[k] <= budget) keep(k);
+      if (total + meas[k].x <= budget) keep(k);
   }
   uint4* d_info = nullptr;
   uint4* d_ent = nullptr;
-  if ((e = hipMalloc((void**)&d_info, m * sizeof(uint4))) != hipSuccess) return hipf(e, "allocation");
+  if ((e = hipMalloc((void**)&d_info, 2 * m * sizeof(uint4))) != hipSuccess) return hipf(e, "allocation");
   g.pair_info = d_info;
   if ((e = hipMalloc((void**)&d_ent, (total ? total : 1) * sizeof(uint4))) != hipSuccess) return hipf(e, "allocation");
   g.pair_ent = d_ent;
-  if ((e = hipMemcpy(d_info, info.data(), m * sizeof(uint4), hipMemcpyHostToDevice)) != hipSuccess ||
+  if ((e = hipMemcpy(d_info, info.data(), 2 * m * sizeof(uint4), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = launch_edge_lists_fill(g.O, g.D, d_src, m, (const uint32_t*)g.R, d_info, d_ent, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return hipf(e, "edge list fill");
-  gr->owned_bytes += m * sizeof(uint4) + total * sizeof(uint4);
+  gr->owned_bytes += 2 * m * sizeof(uint4) + total * sizeof(uint4);
   gr->pair_lists = kept;
   gr->pair_entries = total;
   return N2V_OK;

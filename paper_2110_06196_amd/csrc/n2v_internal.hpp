@@ -35,10 +35,11 @@ struct GraphDev {
   const int32_t* HD = nullptr;
   // Stored common-neighbour lists of edges (weighted graphs with 32-bit
   // prefixes, see n2v_pairs.hip), indexed by the edge's CSR position e
-  // (t -> v = D[e]): pair_info[e] = {first entry lo, first entry hi, entries,
-  // position of t in N(v) or ~0}, first entry ~0 when the list is not kept;
-  // pair_ent = entries {R_v[j], inclusive listed weight, j, 0} in increasing
-  // j.  Null when the graph has none.
+  // (t -> v = D[e]): pair_info[2e] = {first entry, entries, position of t in
+  // N(v) or ~0, total listed weight}, pair_info[2e + 1] = {weight of t in
+  // N(v), 0, 0, 0}; first entry ~0 when the list is not kept; pair_ent =
+  // entries {R_v[j], inclusive listed weight, j, 0} in increasing j.  Null
+  // when the graph has none.
   const uint4* pair_info = nullptr;
   const uint4* pair_ent = nullptr;
 };
@@ -152,8 +153,8 @@ hipError_t launch_prefix_heads(const void* R, uint32_t r_bytes, uint64_t m, void
 // HD[i] = D[32 i] for i < ceil(m / 32).
 hipError_t launch_dest_heads(const int32_t* D, uint64_t m, int32_t* HD, hipStream_t st);
 // Passes of the edge-list builder (n2v_pairs.hip).
-hipError_t launch_edge_lists_measure(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m, uint32_t* cnt,
-                                     uint32_t* ptpos, hipStream_t st);
+hipError_t launch_edge_lists_measure(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m,
+                                     const uint32_t* R, uint4* meas, hipStream_t st);
 hipError_t launch_edge_lists_fill(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m,
                                   const uint32_t* R, const uint4* info, uint4* ent, hipStream_t st);
 hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,

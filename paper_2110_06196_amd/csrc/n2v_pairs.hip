@@ -11,7 +11,10 @@
 // (v = D[e], e in t's row), and the walk kernels read it instead of
 // rebuilding it.  Each entry is {R_v[j], inclusive prefix of the listed
 // weights, j, 0}: exactly the values the list routes compute, so walks stay
-// bit-identical.
+// bit-identical.  Each edge has a 32-byte record {first entry, entries,
+// position of t in N(v) or ~0, total listed weight} {weight of t in N(v), 0,
+// 0, 0}, so a step reads everything it needs before the draw in one line;
+// first entry ~0 marks an edge whose list is not kept.
 //
 // Passes (one wavefront per edge; the lanes split the shorter of N(t) and
 // N(v) and bisect the other; walking N(t) yields the positions in N(v) in
@@ -71,25 +74,31 @@ __device__ __forceinline__ EdgeRows edge_rows(const uint64_t* __restrict__ O, co
   return r;
 }
 
+// Per edge: {entries, position of t in N(v) or ~0, total listed weight,
+// weight of t in N(v) (0 when t is not in it)}.
 __global__ __launch_bounds__(256) void k_edge_lists_measure(const uint64_t* __restrict__ O,
                                                             const int32_t* __restrict__ D,
                                                             const int32_t* __restrict__ src, uint64_t m,
-                                                            uint32_t* __restrict__ cnt,
-                                                            uint32_t* __restrict__ ptpos) {
+                                                            const uint32_t* __restrict__ R,
+                                                            uint4* __restrict__ meas) {
   const int lane = threadIdx.x & 63;
   for (uint64_t e = (uint64_t)wave_index(); e < m; e += (uint64_t)wave_count()) {
     const EdgeRows r = edge_rows(O, D, src, e);
-    uint32_t c = 0;
+    uint32_t c = 0, cw = 0;
     const uint32_t span = r.dt <= r.dv ? r.dt : r.dv;
     if (r.dv > 0) {
       for (uint32_t c0 = 0; c0 < span; c0 += 64) {
-        uint32_t p;
-        c += (uint32_t)__popcll(__ballot(chunk_hit(D, r, c0 + lane, &p)));
+        uint32_t p = 0;
+        const bool hit = chunk_hit(D, r, c0 + lane, &p);
+        const uint32_t w = hit ? (p ? R[r.lov + p] - R[r.lov + p - 1] : R[r.lov + p]) : 0u;
+        c += (uint32_t)__popcll(__ballot(hit));
+        cw += (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_u32(w), 63);
       }
     }
     if (lane == 0) {
-      cnt[e] = c;
-      ptpos[e] = r.dv > 0 ? find_in_row(D + r.lov, r.dv, r.t) : 0xFFFFFFFFu;
+      const uint32_t pt = r.dv > 0 ? find_in_row(D + r.lov, r.dv, r.t) : 0xFFFFFFFFu;
+      const uint32_t wt = pt == 0xFFFFFFFFu ? 0u : (pt ? R[r.lov + pt] - R[r.lov + pt - 1] : R[r.lov + pt]);
+      meas[e] = make_uint4(c, pt, cw, wt);
     }
   }
 }
@@ -101,9 +110,9 @@ __global__ __launch_bounds__(256) void k_edge_lists_fill(const uint64_t* __restr
   const int lane = threadIdx.x & 63;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   for (uint64_t e = (uint64_t)wave_index(); e < m; e += (uint64_t)wave_count()) {
-    const uint4 inf = info[e];
-    if ((inf.x & inf.y) == 0xFFFFFFFFu || inf.z == 0) continue;  // not kept, or empty
-    const uint64_t off = (uint64_t)inf.x | ((uint64_t)inf.y << 32);
+    const uint4 inf = info[2 * e];
+    if (inf.x == 0xFFFFFFFFu || inf.y == 0) continue;  // not kept, or empty
+    const uint64_t off = inf.x;
     const EdgeRows r = edge_rows(O, D, src, e);
     const uint32_t span = r.dt <= r.dv ? r.dt : r.dv;
     uint64_t k = 0;
@@ -130,9 +139,9 @@ unsigned edge_blocks(uint64_t edges) {
 
 }  // namespace
 
-hipError_t launch_edge_lists_measure(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m, uint32_t* cnt,
-                                     uint32_t* ptpos, hipStream_t st) {
-  hipLaunchKernelGGL(k_edge_lists_measure, dim3(edge_blocks(m)), dim3(256), 0, st, O, D, src, m, cnt, ptpos);
+hipError_t launch_edge_lists_measure(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m,
+                                     const uint32_t* R, uint4* meas, hipStream_t st) {
+  hipLaunchKernelGGL(k_edge_lists_measure, dim3(edge_blocks(m)), dim3(256), 0, st, O, D, src, m, R, meas);
   return hipGetLastError();
 }
 

@@ -493,14 +493,15 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           bool cached = false;
           if constexpr (WEIGHTED && sizeof(RT) == 4) {
             if (a.g.pair_info != nullptr && mode_knob == kModeAuto) {
-              const uint4 inf = a.g.pair_info[epos];
-              cached = (inf.x & inf.y) != 0xFFFFFFFFu;
+              const uint4 inf = a.g.pair_info[2 * epos];
+              const uint32_t wtc = a.g.pair_info[2 * epos + 1].x;
+              cached = inf.x != 0xFFFFFFFFu;
               if (cached) {
-                const uint4* __restrict__ ent = a.g.pair_ent + ((uint64_t)inf.x | ((uint64_t)inf.y << 32));
-                const uint32_t nc = inf.z, ptc = inf.w;
+                const uint4* __restrict__ ent = a.g.pair_ent + inf.x;
+                const uint32_t nc = inf.y, ptc = inf.z;
                 const bool has_t = ptc != 0xFFFFFFFFu;
-                const uint64_t CW = nc ? (uint64_t)ent[nc - 1].y : 0ull;
-                const uint64_t retw = has_t ? rdel * Wv(ptc) : 0ull;
+                const uint64_t CW = inf.w;
+                const uint64_t retw = rdel * (uint64_t)wtc;  // wtc = 0 when t is not in N(v)
                 const uint64_t total = Q16 * S + cdel * CW + retw;
                 if (total == 0) break;
                 const uint64_t T = scale_draw(r, total);
