@@ -318,8 +318,20 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
       int32_t* cur = bufA;  // N(t) when staged
       int32_t* nxt = bufB;  // N(v) being staged
       for (uint32_t s = 1; s < a.L; ++s) {
-        const uint64_t lo = O[v];
-        const uint32_t d = (uint32_t)(O[v + 1] - lo);
+        // row offset, degree and row weight sum: one 16-byte node record when
+        // the graph has them, else the offsets and the row's last prefix entry
+        uint64_t lo, Srec = 0;
+        uint32_t d;
+        constexpr bool kRec = WEIGHTED && sizeof(RT) == 4;
+        if (kRec && a.g.NR) {
+          const uint4 rec = a.g.NR[v];
+          lo = (uint64_t)rec.x | ((uint64_t)rec.y << 32);
+          d = rec.z;
+          Srec = rec.w;
+        } else {
+          lo = O[v];
+          d = (uint32_t)(O[v + 1] - lo);
+        }
         if (d == 0) break;  // dead end
         const uint64_t r = philox_draw(a.seed, s, wid);
         auto Rv = [&](uint32_t j) -> uint64_t {
@@ -332,7 +344,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           const uint64_t hi = (uint64_t)R[lo + j];
           return j ? hi - (uint64_t)R[lo + j - 1] : hi;
         };
-        const uint64_t S = Rv(d - 1);  // row weight sum
+        const uint64_t S = (kRec && a.g.NR) ? Srec : Rv(d - 1);  // row weight sum
         uint32_t jsel = 0xFFFFFFFFu;
         bool staged = false;
         bool stop = false;
