@@ -196,17 +196,57 @@ __device__ __forceinline__ uint32_t gary_first(uint32_t lo, uint32_t hi, int gl,
   return m ? lo + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
 }
 
+// gary_first that also reads the destination row X[j] in its final round, so
+// that the chosen candidate's destination comes with the search; xok is false
+// when no index in [lo, hi) satisfies pred (then the caller reads it).
+template <int G, typename P>
+__device__ __forceinline__ uint32_t gary_first_x(uint32_t lo, uint32_t hi, int gl, int gbase, P pred,
+                                                 const int32_t* __restrict__ X, int32_t& xo, bool& xok) {
+  while (hi - lo > (uint32_t)G) {
+    const uint32_t step = (hi - lo + G - 1) / G;
+    const uint32_t j = lo + (uint32_t)(gl + 1) * step - 1;
+    const bool real = j < hi;
+    const bool pr = real ? pred(j) : true;
+    const uint64_t m = grp_ballot<G>(pr, gbase);
+    if (m == 0) {
+      xok = false;
+      return hi;
+    }
+    const int f = __ffsll((unsigned long long)m) - 1;
+    const uint32_t jf = (uint32_t)grp_bcast_i32<G>((int32_t)j, f);
+    lo = lo + (uint32_t)f * step;
+    if (jf < hi) hi = jf;
+  }
+  const uint32_t j = lo + (uint32_t)gl;
+  bool pr = false;
+  int32_t xv = 0;
+  if (j < hi) {
+    pr = pred(j);
+    xv = X[j];
+  }
+  const uint64_t m = grp_ballot<G>(pr, gbase);
+  xok = m != 0;
+  if (!xok) return hi;
+  const int f = __ffsll((unsigned long long)m) - 1;
+  xo = grp_bcast_i32<G>(xv, f);
+  return lo + (uint32_t)f;
+}
+
 // gary_first over a row of a prefix array V (positions lo + j) with a
 // predicate on (V[lo + j], j), monotone in j, through the row's heads
 // H[b] = V[32 b]: a long range first searches the heads of its whole 32-entry
 // blocks (contiguous: a few lines instead of one line per probe), then the
 // at most 32 entries between the last false head and the first true one.
+//
+// X, when given, is the row's destination array (X[j] = D[lo + j]): the
+// destination of the answer is returned in xo (xok true) from the final round.
 template <int G, typename RT, typename P>
 __device__ __forceinline__ uint32_t gary_first_heads(const RT* __restrict__ V, const RT* __restrict__ H, uint64_t lo,
-                                                     uint32_t jlo, uint32_t jhi, int gl, int gbase, P pred) {
+                                                     uint32_t jlo, uint32_t jhi, int gl, int gbase, P pred,
+                                                     const int32_t* __restrict__ X, int32_t& xo, bool& xok) {
   auto direct = [&](uint32_t j) { return pred((uint64_t)V[lo + j], j); };
   // a range of more than 64 entries holds at least two heads
-  if (H == nullptr || jhi - jlo <= 64u || jhi - jlo <= 2u * G) return gary_first<G>(jlo, jhi, gl, gbase, direct);
+  if (H == nullptr || jhi - jlo <= 64u || jhi - jlo <= 2u * G) return gary_first_x<G>(jlo, jhi, gl, gbase, direct, X, xo, xok);
   const uint64_t a = lo + jlo, e = lo + jhi;
   const uint64_t hb0 = (a + 31) >> 5, hb1 = (e - 1) >> 5;  // blocks whose head lies in [a, e)
   const uint32_t nh = (uint32_t)(hb1 - hb0 + 1);
@@ -224,7 +264,7 @@ __device__ __forceinline__ uint32_t gary_first_heads(const RT* __restrict__ V, c
     sb = ((hb0 + k - 1) << 5) + 1;
     se = ((hb0 + k) << 5) + 1;
   }
-  return gary_first<G>((uint32_t)(sb - lo), (uint32_t)(se - lo), gl, gbase, direct);
+  return gary_first_x<G>((uint32_t)(sb - lo), (uint32_t)(se - lo), gl, gbase, direct, X, xo, xok);
 }
 
 // Splitters of a long sorted row A[0..n) (n >= 4G): the group loads A[l n / G]
@@ -346,6 +386,8 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         };
         const uint64_t S = (kRec && a.g.NR) ? Srec : Rv(d - 1);  // row weight sum
         uint32_t jsel = 0xFFFFFFFFu;
+        int32_t xq = 0;      // D[lo + jsel] when the final search round fetched it
+        bool xq_ok = false;
         bool staged = false;
         bool stop = false;
 
@@ -491,7 +533,8 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           if (S == 0) break;
           const uint64_t T = scale_draw(r, S);
           if (WEIGHTED) {
-            jsel = gary_first_heads<G>(R, HR, lo, 0u, d, gl, gbase, [&](uint64_t v, uint32_t) { return v > T; });
+            jsel = gary_first_heads<G>(
+                R, HR, lo, 0u, d, gl, gbase, [&](uint64_t v, uint32_t) { return v > T; }, D + lo, xq, xq_ok);
           } else {
             jsel = (uint32_t)T;
           }
@@ -536,9 +579,10 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                   seg_lo = ent[nc - 1].z + 1;
                 }
                 const uint64_t base = cdel * Eprev;
-                jsel = gary_first_heads<G>(R, HR, lo, seg_lo, seg_hi, gl, gbase, [&](uint64_t v, uint32_t j) {
-                  return Q16 * v + base + ((has_t && j >= ptc) ? retw : 0ull) > T;
-                });
+                jsel = gary_first_heads<G>(
+                    R, HR, lo, seg_lo, seg_hi, gl, gbase,
+                    [&](uint64_t v, uint32_t j) { return Q16 * v + base + ((has_t && j >= ptc) ? retw : 0ull) > T; },
+                    D + lo, xq, xq_ok);
               }
             }
           }
@@ -788,9 +832,10 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             }
             const uint64_t base = cdel * Eprev;
             if constexpr (WEIGHTED) {
-              jsel = gary_first_heads<G>(R, HR, lo, seg_lo, seg_hi, gl, gbase, [&](uint64_t v, uint32_t j) {
-                return Q16 * v + base + ((has_t && j >= pt) ? retw : 0ull) > T;
-              });
+              jsel = gary_first_heads<G>(
+                  R, HR, lo, seg_lo, seg_hi, gl, gbase,
+                  [&](uint64_t v, uint32_t j) { return Q16 * v + base + ((has_t && j >= pt) ? retw : 0ull) > T; },
+                  D + lo, xq, xq_ok);
             } else {
               jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
                 return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
@@ -800,7 +845,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           }
         }
         if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
-        const int32_t xsel = D[lo + jsel];
+        const int32_t xsel = xq_ok ? xq : D[lo + jsel];
 
         if ((uint32_t)gl == s % G) ob = xsel;
         if (s % G == G - 1) {
