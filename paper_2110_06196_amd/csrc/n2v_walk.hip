@@ -232,6 +232,49 @@ __device__ __forceinline__ uint32_t gary_first_x(uint32_t lo, uint32_t hi, int g
   return lo + (uint32_t)f;
 }
 
+// First k in [0, nc) whose stored list entry satisfies pred (monotone in k),
+// or nc, by G-ary rounds; the final round's window starts one entry early, so
+// the entries at k and k - 1 (when they exist) come with it: ek = entry k
+// (k < nc), ekm = entry k - 1 (k > 0).
+template <int G, typename P>
+__device__ __forceinline__ uint32_t list_search(const uint4* __restrict__ ent, uint32_t nc, int gl, int gbase, P pred,
+                                                uint4& ek, uint4& ekm) {
+  uint32_t lo = 0, hi = nc;
+  while (hi - lo > (uint32_t)G - 2u) {
+    const uint32_t step = (hi - lo + G - 1) / G;
+    const uint32_t j = lo + (uint32_t)(gl + 1) * step - 1;
+    const bool pr = j < hi ? pred(ent[j]) : true;
+    const uint64_t m = grp_ballot<G>(pr, gbase);
+    if (m == 0) {  // every probe false, the last one at hi - 1: the answer is hi
+      lo = hi;
+      break;
+    }
+    const int f = __ffsll((unsigned long long)m) - 1;
+    const uint32_t jf = (uint32_t)grp_bcast_i32<G>((int32_t)j, f);
+    lo = lo + (uint32_t)f * step;
+    if (jf < hi) hi = jf;
+  }
+  // window [b, b + G) holds lo - 1 .. hi (hi - lo <= G - 2); hi is true or nc
+  const uint32_t b = lo > 0 ? lo - 1 : 0u;
+  const uint32_t j = b + (uint32_t)gl;
+  uint4 en = make_uint4(0u, 0u, 0u, 0u);
+  if (j < nc) en = ent[j];
+  const bool pr = j >= lo && j < hi && pred(en);
+  const uint64_t m = grp_ballot<G>(pr, gbase);
+  const uint32_t k = m ? b + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
+  auto take = [&](uint32_t lane_idx) {
+    uint4 r;
+    r.x = (uint32_t)grp_bcast_i32<G>((int32_t)en.x, (int)lane_idx);
+    r.y = (uint32_t)grp_bcast_i32<G>((int32_t)en.y, (int)lane_idx);
+    r.z = (uint32_t)grp_bcast_i32<G>((int32_t)en.z, (int)lane_idx);
+    r.w = 0u;
+    return r;
+  };
+  if (k < nc) ek = take(k - b);
+  if (k > 0) ekm = take(k - 1 - b);
+  return k;
+}
+
 // gary_first over a row of a prefix array V (positions lo + j) with a
 // predicate on (V[lo + j], j), monotone in j, through the row's heads
 // H[b] = V[32 b]: a long range first searches the heads of its whole 32-entry
@@ -561,22 +604,21 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                 if (total == 0) break;
                 const uint64_t T = scale_draw(r, total);
                 // first listed entry with B > T, B = Q16 R_j + cdel E_j + retw [j >= pt]
-                const uint32_t k = gary_first<G>(0u, nc, gl, gbase, [&](uint32_t i) {
-                  const uint4 en = ent[i];
+                uint4 ek, ekm;
+                const uint32_t k = list_search<G>(ent, nc, gl, gbase, [&](const uint4& en) {
                   return Q16 * (uint64_t)en.x + cdel * (uint64_t)en.y + ((has_t && en.z >= ptc) ? retw : 0ull) > T;
-                });
+                }, ek, ekm);
                 uint32_t seg_lo = 0, seg_hi = d;
                 uint64_t Eprev = CW;
                 if (k < nc) {
-                  seg_hi = ent[k].z;
+                  seg_hi = ek.z;
                   Eprev = 0;
                   if (k > 0) {
-                    const uint4 ep = ent[k - 1];
-                    seg_lo = ep.z + 1;
-                    Eprev = ep.y;
+                    seg_lo = ekm.z + 1;
+                    Eprev = ekm.y;
                   }
                 } else if (nc > 0) {
-                  seg_lo = ent[nc - 1].z + 1;
+                  seg_lo = ekm.z + 1;
                 }
                 const uint64_t base = cdel * Eprev;
                 jsel = gary_first_heads<G>(
