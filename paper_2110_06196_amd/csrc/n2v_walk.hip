@@ -629,261 +629,261 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
             }
           }
           if (!cached) {
-          int mode = mode_knob;
-          if (mode == kModeAuto) {
-            // dependent-latency estimate: global load = 100, LDS load = 15
-            // splitters cut a bisection of a row of n >= 4G by log2(G) global rounds for one round
-            auto glob = [&](uint32_t n) -> uint32_t {
-              return n >= 4u * G ? 100u * (ceil_log2p1(n) - ceil_log2p1(G - 1)) + 15u * ceil_log2p1(G) : 100u * ceil_log2p1(n);
-            };
-            const uint64_t probe = (uint64_t)((td + 1 + G - 1) / G) * glob(d) + (d >= 4u * G ? 100u : 0u);
-            const uint64_t stream = (uint64_t)((d + G - 1) / G) *
-                                        (100u + (t_in_lds ? 15u * ceil_log2p1(td) : glob(td))) +
-                                    (!t_in_lds && td >= 4u * G ? 100u : 0u);
-            const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) * (t_in_lds ? 150u : 240u);
-            mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
-                                  : (stream <= merge ? kModeStream : kModeMerge);
-          }
-          if (FULL && mode == kModeTwoPass) {
-            if constexpr (FULL) two_pass();
-          } else {
-            // List the positions j in N(v) whose candidate is a common
-            // neighbour (x in N(t), x != t), in increasing j, one LDS page of
-            // `cap` entries at a time.  Every route visits keys in an order
-            // that makes the hit positions increase, so a page can be resumed
-            // from the key after its last stored hit.
-            uint32_t cnt = 0, pt = 0, stored = 0, resume = 0;
-            bool has_t = false, first = true;
-            uint64_t acc = 0;
-            auto append = [&](bool hit, uint32_t pos, uint32_t key0) {
-              const uint64_t m = grp_ballot<G>(hit, gbase);
-              if (m == 0) return;
-              if (hit) {
-                // a listed position gets its weight after the route (below);
-                // a hit beyond the page adds its weight to the first pass's sum now
-                const uint32_t idx = stored + (uint32_t)__popcll(m & lt_mask);
-                if (idx < (uint32_t)cap) lpos[idx] = pos;
-                else if (first) acc += (uint32_t)Wv(pos);
-              }
-              const uint32_t nh = (uint32_t)__popcll(m);
-              const uint32_t room = (uint32_t)cap - stored;
-              if (room > 0 && nh >= room) {
-                uint64_t mm = m;  // the room-th hit fills the page's last slot
-                for (uint32_t i = 1; i < room; ++i) mm &= mm - 1;
-                resume = key0 + (uint32_t)(__ffsll((unsigned long long)mm) - 1) + 1;
-              }
-              cnt += nh;
-              stored = min((uint32_t)cap, stored + nh);
-            };
-            // keys [from, end): probe route keys are N(t) then t itself; stream
-            // route keys are the candidates of N(v).  Later pages stop once full.
-            auto gen = [&](uint32_t from) {
-              if (mode == kModeProbe) {
-                const uint32_t nk = td + 1;
-                const bool split = d >= 4u * G;
-                if (split) load_splitters<G>(D + lo, d, win, gl);
-                for (uint32_t c = from; c < nk; c += G) {
-                  if (!first && stored >= (uint32_t)cap) break;
-                  const uint32_t k = c + gl;
-                  const bool act = k < nk;
-                  const bool tkey = k == td;
-                  int32_t y = t;
-                  if (act && !tkey) y = t_in_lds ? cur[k] : D[tlo + k];
-                  uint32_t pos = 0;
-                  bool hit = false;
-                  if (act) {
-                    int32_t val;
-                    pos = split ? split_floor<G>(D, HD, lo, d, win, y, val) : floor_search(D + lo, 0u, d, D[lo], y, val);
-                    hit = val == y;
-                  }
-                  const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
-                  if (mt) {
-                    has_t = true;
-                    pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
-                  }
-                  // a self-loop at t puts t in N(t): that candidate is a return, not common
-                  append(hit && !tkey && y != t, pos, c);
-                }
-              } else if (mode == kModeMerge) {
-                // co-iterate N(v) (candidates, global) and N(t) (B): invariant
-                // "every element of B before ib is below N(v)[ia]".  A round
-                // stages 2G elements of B in LDS, takes 2G candidates (two per
-                // lane), decides every candidate that is at most the window's
-                // last element by bisecting the window, and advances ia past
-                // the decided candidates, or ib by 2G when some candidate lies
-                // beyond the window.
-                constexpr uint32_t W2 = 2u * G;
-                const bool stg = first && d <= (uint32_t)tile;
-                auto Bv = [&](uint32_t k) -> int32_t { return t_in_lds ? cur[k] : D[tlo + k]; };
-                uint32_t ia = from, ib = 0;
-                if (ia > 0 && ia < d) {
-                  const int32_t a0 = D[lo + ia];
-                  ib = gary_first<G>(0u, td, gl, gbase, [&](uint32_t k) { return Bv(k) >= a0; });
-                }
-                while (ia < d) {
-                  if (!first && stored >= (uint32_t)cap) break;
-                  const uint32_t j0 = ia + gl, j1 = j0 + G;
-                  const bool act0 = j0 < d, act1 = j1 < d;
-                  int32_t x0 = 0x7FFFFFFF, x1 = 0x7FFFFFFF;
-                  if (act0) x0 = D[lo + j0];
-                  if (act1) x1 = D[lo + j1];
-                  const uint32_t nb = ib < td ? min(W2, td - ib) : 0u;
-                  const int32_t b0 = (uint32_t)gl < nb ? Bv(ib + gl) : 0x7FFFFFFF;
-                  const int32_t b1 = (uint32_t)gl + G < nb ? Bv(ib + G + gl) : 0x7FFFFFFF;
-                  if (stg) {
-                    if (act0) nxt[j0] = x0;
-                    if (act1) nxt[j1] = x1;
-                  }
-                  win[gl] = b0;
-                  win[G + gl] = b1;
-                  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                  // B beyond this window is empty when nb < 2G: then every candidate is decided
-                  const int32_t blast = nb == W2 ? grp_bcast_i32<G>(b1, G - 1) : 0x7FFFFFFF;
-                  const bool res0 = act0 && x0 <= blast, res1 = act1 && x1 <= blast;
-                  const bool ret0 = res0 && x0 == t, ret1 = res1 && x1 == t;
-                  const uint64_t mt0 = grp_ballot<G>(ret0, gbase), mt1 = grp_ballot<G>(ret1, gbase);
-                  if (mt0 | mt1) {
-                    has_t = true;
-                    pt = mt0 ? ia + (uint32_t)(__ffsll((unsigned long long)mt0) - 1)
-                             : ia + G + (uint32_t)(__ffsll((unsigned long long)mt1) - 1);
-                  }
-                  const bool in0 = res0 && !ret0 && nb > 0 && lds_contains(win, nb, x0);
-                  const bool in1 = res1 && !ret1 && nb > 0 && lds_contains(win, nb, x1);
-                  append(in0, j0, ia);
-                  append(in1, j1, ia + G);
-                  const uint32_t nact = min(W2, d - ia);
-                  const uint32_t nres = (uint32_t)__popcll(grp_ballot<G>(res0, gbase)) +
-                                        (uint32_t)__popcll(grp_ballot<G>(res1, gbase));
-                  if (nres == nact) {
-                    ia += nact;
-                  } else {
-                    ia += nres;  // decided candidates are a prefix: the candidates are sorted
-                    ib += W2;
-                  }
-                  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
-                if (first) staged = stg;
-              } else {
-                const bool stg = first && d <= (uint32_t)tile;
-                const bool split = !t_in_lds && td >= 4u * G;
-                if (split) load_splitters<G>(D + tlo, td, win, gl);
-                for (uint32_t c = from; c < d; c += G) {
-                  if (!first && stored >= (uint32_t)cap) break;
-                  const uint32_t j = c + gl;
-                  const bool act = j < d;
-                  int32_t x = 0;
-                  if (act) {
-                    x = D[lo + j];
-                    if (stg) nxt[j] = x;
-                  }
-                  const bool isret = act && x == t;
-                  const uint64_t mt = grp_ballot<G>(isret, gbase);
-                  if (mt) {
-                    has_t = true;
-                    pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
-                  }
-                  bool in_t;
-                  if (t_in_lds) {
-                    in_t = act && !isret && lds_contains(cur, td, x);
-                  } else {
-                    if (split) {
-                      in_t = false;
-                      if (act && !isret) {
-                        int32_t val;
-                        split_floor<G>(D, HD, tlo, td, win, x, val);
-                        in_t = val == x;
-                      }
-                    } else {
-                      in_t = act && !isret && global_contains(D + tlo, td, x);
-                    }
-                  }
-                  append(act && !isret && in_t, j, c);
-                }
-                if (first) staged = stg;
-              }
-              // Weights of the page's positions: one gather over the list, off the
-              // chain of dependent loads of the route's rounds.
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-              for (uint32_t k = gl; k < stored; k += 2 * G) {
-                const uint32_t k2 = k + G;
-                const bool two = k2 < stored;
-                const uint32_t w1 = (uint32_t)Wv(lpos[k]);
-                const uint32_t w2 = two ? (uint32_t)Wv(lpos[k2]) : 0u;
-                lw[k] = w1;
-                if (two) lw[k2] = w2;
-                if (first) acc += (uint64_t)w1 + w2;
-              }
-              // the page is read by other lanes of the group
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            };
-            gen(0);  // first pass: every hit counted, first page stored
-            first = false;
-            const uint64_t CW = grp_sum<G>(acc);
-            const uint64_t wt = has_t ? Wv(pt) : 0ull;
-            const uint64_t retw = rdel * wt;
-            const uint64_t total = Q16 * S + cdel * CW + retw;
-            if (total == 0) break;
-            const uint64_t T = scale_draw(r, total);
-            // B_j = Q16 R_j + cdel * (common weight up to j) + retw [j >= pt]:
-            // find the first listed position with B > T, then the segment
-            // before it holds no common neighbour.
-            uint64_t E = 0, Eprev = CW;
-            uint32_t seg_lo = 0, seg_hi = d, lastpos = 0, left = cnt, page = stored;
-            bool found = false, any = false;
-            while (true) {
-              for (uint32_t c = 0; c < page; c += G) {
-                const uint32_t k = c + gl;
-                const bool act = k < page;
-                const uint32_t p = act ? lpos[k] : 0u;
-                const uint64_t wk = act ? (uint64_t)lw[k] : 0ull;
-                const uint64_t inc = grp_incl_scan<G>(wk, gl);
-                const uint64_t Ek = E + inc;
-                const uint64_t Bk = Q16 * Rv(p) + cdel * Ek + ((has_t && p >= pt) ? retw : 0ull);
-                const uint64_t m = grp_ballot<G>(act && Bk > T, gbase);
-                if (m) {
-                  const int f = __ffsll((unsigned long long)m) - 1;
-                  Eprev = grp_bcast<G>(Ek - wk, f);
-                  seg_hi = (uint32_t)grp_bcast_i32<G>((int32_t)p, f);
-                  const uint32_t pprev = (uint32_t)grp_bcast_i32<G>((int32_t)p, f > 0 ? f - 1 : 0);
-                  seg_lo = f > 0 ? pprev + 1 : (any ? lastpos + 1 : 0u);
-                  found = true;
-                  break;
-                }
-                const uint32_t nact = min((uint32_t)G, page - c);
-                lastpos = (uint32_t)grp_bcast_i32<G>((int32_t)p, (int)nact - 1);
-                any = true;
-                E += grp_bcast<G>(inc, G - 1);
-              }
-              left -= page;
-              if (found || left == 0) break;
-              // the draw lies beyond this page: list the next one
-              stored = 0;
-              const uint32_t from = resume;
-              gen(from);
-              page = stored;
-              if (page == 0) break;  // unreachable: `left` hits remain after `from`
+            int mode = mode_knob;
+            if (mode == kModeAuto) {
+              // dependent-latency estimate: global load = 100, LDS load = 15
+              // splitters cut a bisection of a row of n >= 4G by log2(G) global rounds for one round
+              auto glob = [&](uint32_t n) -> uint32_t {
+                return n >= 4u * G ? 100u * (ceil_log2p1(n) - ceil_log2p1(G - 1)) + 15u * ceil_log2p1(G) : 100u * ceil_log2p1(n);
+              };
+              const uint64_t probe = (uint64_t)((td + 1 + G - 1) / G) * glob(d) + (d >= 4u * G ? 100u : 0u);
+              const uint64_t stream = (uint64_t)((d + G - 1) / G) *
+                                          (100u + (t_in_lds ? 15u * ceil_log2p1(td) : glob(td))) +
+                                      (!t_in_lds && td >= 4u * G ? 100u : 0u);
+              const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) * (t_in_lds ? 150u : 240u);
+              mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
+                                    : (stream <= merge ? kModeStream : kModeMerge);
             }
-            if (!found) {
-              seg_lo = any ? lastpos + 1 : 0u;
-              seg_hi = d;
-              Eprev = CW;
-            }
-            const uint64_t base = cdel * Eprev;
-            if constexpr (WEIGHTED) {
-              jsel = gary_first_heads<G>(
-                  R, HR, lo, seg_lo, seg_hi, gl, gbase,
-                  [&](uint64_t v, uint32_t j) { return Q16 * v + base + ((has_t && j >= pt) ? retw : 0ull) > T; },
-                  D + lo, xq, xq_ok);
+            if (FULL && mode == kModeTwoPass) {
+              if constexpr (FULL) two_pass();
             } else {
-              jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
-                return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
-              });
+              // List the positions j in N(v) whose candidate is a common
+              // neighbour (x in N(t), x != t), in increasing j, one LDS page of
+              // `cap` entries at a time.  Every route visits keys in an order
+              // that makes the hit positions increase, so a page can be resumed
+              // from the key after its last stored hit.
+              uint32_t cnt = 0, pt = 0, stored = 0, resume = 0;
+              bool has_t = false, first = true;
+              uint64_t acc = 0;
+              auto append = [&](bool hit, uint32_t pos, uint32_t key0) {
+                const uint64_t m = grp_ballot<G>(hit, gbase);
+                if (m == 0) return;
+                if (hit) {
+                  // a listed position gets its weight after the route (below);
+                  // a hit beyond the page adds its weight to the first pass's sum now
+                  const uint32_t idx = stored + (uint32_t)__popcll(m & lt_mask);
+                  if (idx < (uint32_t)cap) lpos[idx] = pos;
+                  else if (first) acc += (uint32_t)Wv(pos);
+                }
+                const uint32_t nh = (uint32_t)__popcll(m);
+                const uint32_t room = (uint32_t)cap - stored;
+                if (room > 0 && nh >= room) {
+                  uint64_t mm = m;  // the room-th hit fills the page's last slot
+                  for (uint32_t i = 1; i < room; ++i) mm &= mm - 1;
+                  resume = key0 + (uint32_t)(__ffsll((unsigned long long)mm) - 1) + 1;
+                }
+                cnt += nh;
+                stored = min((uint32_t)cap, stored + nh);
+              };
+              // keys [from, end): probe route keys are N(t) then t itself; stream
+              // route keys are the candidates of N(v).  Later pages stop once full.
+              auto gen = [&](uint32_t from) {
+                if (mode == kModeProbe) {
+                  const uint32_t nk = td + 1;
+                  const bool split = d >= 4u * G;
+                  if (split) load_splitters<G>(D + lo, d, win, gl);
+                  for (uint32_t c = from; c < nk; c += G) {
+                    if (!first && stored >= (uint32_t)cap) break;
+                    const uint32_t k = c + gl;
+                    const bool act = k < nk;
+                    const bool tkey = k == td;
+                    int32_t y = t;
+                    if (act && !tkey) y = t_in_lds ? cur[k] : D[tlo + k];
+                    uint32_t pos = 0;
+                    bool hit = false;
+                    if (act) {
+                      int32_t val;
+                      pos = split ? split_floor<G>(D, HD, lo, d, win, y, val) : floor_search(D + lo, 0u, d, D[lo], y, val);
+                      hit = val == y;
+                    }
+                    const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
+                    if (mt) {
+                      has_t = true;
+                      pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
+                    }
+                    // a self-loop at t puts t in N(t): that candidate is a return, not common
+                    append(hit && !tkey && y != t, pos, c);
+                  }
+                } else if (mode == kModeMerge) {
+                  // co-iterate N(v) (candidates, global) and N(t) (B): invariant
+                  // "every element of B before ib is below N(v)[ia]".  A round
+                  // stages 2G elements of B in LDS, takes 2G candidates (two per
+                  // lane), decides every candidate that is at most the window's
+                  // last element by bisecting the window, and advances ia past
+                  // the decided candidates, or ib by 2G when some candidate lies
+                  // beyond the window.
+                  constexpr uint32_t W2 = 2u * G;
+                  const bool stg = first && d <= (uint32_t)tile;
+                  auto Bv = [&](uint32_t k) -> int32_t { return t_in_lds ? cur[k] : D[tlo + k]; };
+                  uint32_t ia = from, ib = 0;
+                  if (ia > 0 && ia < d) {
+                    const int32_t a0 = D[lo + ia];
+                    ib = gary_first<G>(0u, td, gl, gbase, [&](uint32_t k) { return Bv(k) >= a0; });
+                  }
+                  while (ia < d) {
+                    if (!first && stored >= (uint32_t)cap) break;
+                    const uint32_t j0 = ia + gl, j1 = j0 + G;
+                    const bool act0 = j0 < d, act1 = j1 < d;
+                    int32_t x0 = 0x7FFFFFFF, x1 = 0x7FFFFFFF;
+                    if (act0) x0 = D[lo + j0];
+                    if (act1) x1 = D[lo + j1];
+                    const uint32_t nb = ib < td ? min(W2, td - ib) : 0u;
+                    const int32_t b0 = (uint32_t)gl < nb ? Bv(ib + gl) : 0x7FFFFFFF;
+                    const int32_t b1 = (uint32_t)gl + G < nb ? Bv(ib + G + gl) : 0x7FFFFFFF;
+                    if (stg) {
+                      if (act0) nxt[j0] = x0;
+                      if (act1) nxt[j1] = x1;
+                    }
+                    win[gl] = b0;
+                    win[G + gl] = b1;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    // B beyond this window is empty when nb < 2G: then every candidate is decided
+                    const int32_t blast = nb == W2 ? grp_bcast_i32<G>(b1, G - 1) : 0x7FFFFFFF;
+                    const bool res0 = act0 && x0 <= blast, res1 = act1 && x1 <= blast;
+                    const bool ret0 = res0 && x0 == t, ret1 = res1 && x1 == t;
+                    const uint64_t mt0 = grp_ballot<G>(ret0, gbase), mt1 = grp_ballot<G>(ret1, gbase);
+                    if (mt0 | mt1) {
+                      has_t = true;
+                      pt = mt0 ? ia + (uint32_t)(__ffsll((unsigned long long)mt0) - 1)
+                               : ia + G + (uint32_t)(__ffsll((unsigned long long)mt1) - 1);
+                    }
+                    const bool in0 = res0 && !ret0 && nb > 0 && lds_contains(win, nb, x0);
+                    const bool in1 = res1 && !ret1 && nb > 0 && lds_contains(win, nb, x1);
+                    append(in0, j0, ia);
+                    append(in1, j1, ia + G);
+                    const uint32_t nact = min(W2, d - ia);
+                    const uint32_t nres = (uint32_t)__popcll(grp_ballot<G>(res0, gbase)) +
+                                          (uint32_t)__popcll(grp_ballot<G>(res1, gbase));
+                    if (nres == nact) {
+                      ia += nact;
+                    } else {
+                      ia += nres;  // decided candidates are a prefix: the candidates are sorted
+                      ib += W2;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                  }
+                  if (first) staged = stg;
+                } else {
+                  const bool stg = first && d <= (uint32_t)tile;
+                  const bool split = !t_in_lds && td >= 4u * G;
+                  if (split) load_splitters<G>(D + tlo, td, win, gl);
+                  for (uint32_t c = from; c < d; c += G) {
+                    if (!first && stored >= (uint32_t)cap) break;
+                    const uint32_t j = c + gl;
+                    const bool act = j < d;
+                    int32_t x = 0;
+                    if (act) {
+                      x = D[lo + j];
+                      if (stg) nxt[j] = x;
+                    }
+                    const bool isret = act && x == t;
+                    const uint64_t mt = grp_ballot<G>(isret, gbase);
+                    if (mt) {
+                      has_t = true;
+                      pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
+                    }
+                    bool in_t;
+                    if (t_in_lds) {
+                      in_t = act && !isret && lds_contains(cur, td, x);
+                    } else {
+                      if (split) {
+                        in_t = false;
+                        if (act && !isret) {
+                          int32_t val;
+                          split_floor<G>(D, HD, tlo, td, win, x, val);
+                          in_t = val == x;
+                        }
+                      } else {
+                        in_t = act && !isret && global_contains(D + tlo, td, x);
+                      }
+                    }
+                    append(act && !isret && in_t, j, c);
+                  }
+                  if (first) staged = stg;
+                }
+                // Weights of the page's positions: one gather over the list, off the
+                // chain of dependent loads of the route's rounds.
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (uint32_t k = gl; k < stored; k += 2 * G) {
+                  const uint32_t k2 = k + G;
+                  const bool two = k2 < stored;
+                  const uint32_t w1 = (uint32_t)Wv(lpos[k]);
+                  const uint32_t w2 = two ? (uint32_t)Wv(lpos[k2]) : 0u;
+                  lw[k] = w1;
+                  if (two) lw[k2] = w2;
+                  if (first) acc += (uint64_t)w1 + w2;
+                }
+                // the page is read by other lanes of the group
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+              };
+              gen(0);  // first pass: every hit counted, first page stored
+              first = false;
+              const uint64_t CW = grp_sum<G>(acc);
+              const uint64_t wt = has_t ? Wv(pt) : 0ull;
+              const uint64_t retw = rdel * wt;
+              const uint64_t total = Q16 * S + cdel * CW + retw;
+              if (total == 0) break;
+              const uint64_t T = scale_draw(r, total);
+              // B_j = Q16 R_j + cdel * (common weight up to j) + retw [j >= pt]:
+              // find the first listed position with B > T, then the segment
+              // before it holds no common neighbour.
+              uint64_t E = 0, Eprev = CW;
+              uint32_t seg_lo = 0, seg_hi = d, lastpos = 0, left = cnt, page = stored;
+              bool found = false, any = false;
+              while (true) {
+                for (uint32_t c = 0; c < page; c += G) {
+                  const uint32_t k = c + gl;
+                  const bool act = k < page;
+                  const uint32_t p = act ? lpos[k] : 0u;
+                  const uint64_t wk = act ? (uint64_t)lw[k] : 0ull;
+                  const uint64_t inc = grp_incl_scan<G>(wk, gl);
+                  const uint64_t Ek = E + inc;
+                  const uint64_t Bk = Q16 * Rv(p) + cdel * Ek + ((has_t && p >= pt) ? retw : 0ull);
+                  const uint64_t m = grp_ballot<G>(act && Bk > T, gbase);
+                  if (m) {
+                    const int f = __ffsll((unsigned long long)m) - 1;
+                    Eprev = grp_bcast<G>(Ek - wk, f);
+                    seg_hi = (uint32_t)grp_bcast_i32<G>((int32_t)p, f);
+                    const uint32_t pprev = (uint32_t)grp_bcast_i32<G>((int32_t)p, f > 0 ? f - 1 : 0);
+                    seg_lo = f > 0 ? pprev + 1 : (any ? lastpos + 1 : 0u);
+                    found = true;
+                    break;
+                  }
+                  const uint32_t nact = min((uint32_t)G, page - c);
+                  lastpos = (uint32_t)grp_bcast_i32<G>((int32_t)p, (int)nact - 1);
+                  any = true;
+                  E += grp_bcast<G>(inc, G - 1);
+                }
+                left -= page;
+                if (found || left == 0) break;
+                // the draw lies beyond this page: list the next one
+                stored = 0;
+                const uint32_t from = resume;
+                gen(from);
+                page = stored;
+                if (page == 0) break;  // unreachable: `left` hits remain after `from`
+              }
+              if (!found) {
+                seg_lo = any ? lastpos + 1 : 0u;
+                seg_hi = d;
+                Eprev = CW;
+              }
+              const uint64_t base = cdel * Eprev;
+              if constexpr (WEIGHTED) {
+                jsel = gary_first_heads<G>(
+                    R, HR, lo, seg_lo, seg_hi, gl, gbase,
+                    [&](uint64_t v, uint32_t j) { return Q16 * v + base + ((has_t && j >= pt) ? retw : 0ull) > T; },
+                    D + lo, xq, xq_ok);
+              } else {
+                jsel = gary_first<G>(seg_lo, seg_hi, gl, gbase, [&](uint32_t j) {
+                  return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
+                });
+              }
             }
-          }
           }
         }
         if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
