@@ -297,7 +297,7 @@ int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weig
 
 // Stored common-neighbour lists of edges (n2v_pairs.hip), for weighted graphs
 // with 32-bit prefixes and at most kListMaxEntries entries, when measuring
-// them takes at most kListWorkCap bisection reads.  Every edge's list is kept
+// them takes at most kListWorkCap bisection reads and device memory allows.  Every edge's list is kept
 // when all fit the budget of min(kListBudgetMax, 256 m) bytes (16 B per entry,
 // so 16 entries per graph entry); otherwise the edges with the most merge work
 // per stored entry, (d_t + d_v) / (entries + 4), are kept until it is full.
@@ -333,9 +333,15 @@ int build_edge_lists(GraphRec* gr, hipStream_t st) {
   const uint64_t n = gr->n_nodes, m = gr->n_entries;
   if (!g.R || g.r_bytes != 4 || m == 0 || m > kListMaxEntries) return N2V_OK;
   DeviceTemps tmp;
+  // The lists change no walk: when device memory runs short the graph is
+  // registered without them; any other failure is reported.
   auto hipf = [&](hipError_t e, const char* what) -> int {
     free_edge_lists(g);
-    return e == hipErrorOutOfMemory ? fail(N2V_ERR_NOMEM, "edge lists: %s", what) : hip_fail(e, what);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      return N2V_OK;
+    }
+    return hip_fail(e, what);
   };
   std::vector<uint64_t> hO(n + 1);
   std::vector<int32_t> hD(m);
