@@ -10,6 +10,7 @@
 #include <cstring>
 #include <algorithm>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <string>
 #include <unordered_map>
@@ -474,7 +475,14 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
       }
     }
   }
-  if (rc == N2V_OK && !(flags & N2V_UPLOAD_NO_PAIR_LISTS)) rc = build_edge_lists(gr, st);
+  if (rc == N2V_OK && !(flags & N2V_UPLOAD_NO_PAIR_LISTS)) {
+    try {
+      rc = build_edge_lists(gr, st);
+    } catch (const std::bad_alloc&) {  // host memory for the layout: go on without lists
+      free_edge_lists(gr->dev);
+      rc = N2V_OK;
+    }
+  }
   if (rc != N2V_OK) {
     free_record(gr);
     return rc;
