@@ -116,6 +116,22 @@ def traffic_from_profiles(kernel: str, path: str = TRAFFIC_FILE, files=WALK_SOUR
     return float(m.group(1)) if m else None
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "pmc_counters_chung_lu_1m.txt")
+
+
+def l2_hit_from_profiles(kernel: str, path: str = COUNTERS_FILE, files=WALK_SOURCES):
+    """L2 hit rate of `kernel` from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources (else None)."""
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_hash:\s*(\w+)", txt)
+    if not m or m.group(1) != kernel_source_hash(files):
+        return None
+    m = re.search(rf"^{re.escape(kernel)}\s+valu_insts_per_wave:.*l2_hit_rate:\s*([0-9.]+)", txt, re.M)
+    return float(m.group(1)) if m else None
+
+
 def _csvs(d, suffix):
     import glob
     return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
@@ -559,6 +575,7 @@ def main():
         "gather_roofline": {
             "buffer_bytes": ws2, "random_4B_GBps": g4, "random_64B_GBps": g64,
             "kernel_fetch_GBps": (traffic / (dom["mean_ms"] / 1e3) / 1e9) if traffic else None,
+            "kernel_l2_hit_rate": l2_hit_from_profiles(KERNEL_OF_PATH[dom["path"]]),
             "note": "useful GB/s of random 4 B / 64 B reads over a buffer the size of the graph arrays, measured "
                     "in this run, beside the dominant kernel's measured HBM traffic rate (committed PMC profile)",
         },

@@ -64,6 +64,17 @@ def test_traffic_needs_matching_source_hash(tmp_path):
     assert bench.traffic_from_profiles("k_walk_lane", str(f)) is None
 
 
+def test_l2_hit_needs_matching_source_hash(tmp_path):
+    f = tmp_path / "c.txt"
+    line = "k_walk_n2v valu_insts_per_wave: 1.0 vmem_rd_insts_per_wave: 1.0 lds_insts_per_wave: 0.0 " \
+           "wait_any_share_of_wave_cycles: 0.5 l2_hit_rate: 0.375\n"
+    f.write_text("source_hash: 0000000000000000\n" + line)
+    assert bench.l2_hit_from_profiles("k_walk_n2v", str(f)) is None
+    f.write_text(f"source_hash: {bench.kernel_source_hash()}\n" + line)
+    assert bench.l2_hit_from_profiles("k_walk_n2v", str(f)) == 0.375
+    assert bench.l2_hit_from_profiles("k_walk_lane", str(f)) is None
+
+
 def _pmc_csv(d, rows):
     os.makedirs(d, exist_ok=True)
     with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as fh:
