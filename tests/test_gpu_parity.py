@@ -206,6 +206,22 @@ def test_hub_pair_lists_identical():
     n2v.n2v_graph_release(g1)
 
 
+def test_edge_lists_over_budget():
+    """A complete graph has n - 2 common neighbours on every edge, more than the
+    lists' budget of 16 entries per graph entry: only part of the edges keep a
+    list, the others use the routes, and the walks still equal the oracle's."""
+    O, D, _ = synth.complete(40)
+    rng = np.random.default_rng(5)
+    W = rng.integers(1, 50, size=len(D)).astype(np.uint32)
+    g, keep = upload(O, D, W)
+    info = n2v.n2v_graph_info(g)
+    assert 0 < info["pair_lists"] < len(D)
+    for p, q in ((0.25, 4.0), (3.0, 0.3)):
+        check(O, D, W, np.arange(40), 20, 30, NV, p, q, seed=13, g=g)
+    n2v.n2v_graph_release(g)
+    del keep
+
+
 def test_ba_10k_full():
     """Barabasi-Albert, 10,000 nodes, m = 5, node2vec p = 2, q = 0.5, one walk of
     80 slots per node, seed 42: every walk."""
