@@ -26,7 +26,7 @@ struct GraphRec {
   EFDev ef;                  // Elias-Fano store (storage == N2V_STORAGE_EF)
   void* ef_mem = nullptr;    // owned: H, L, S1, S0
   uint32_t ef_quantum = 0;
-  uint64_t pair_lists = 0, pair_entries = 0;  // stored hub-edge lists (n2v_pairs.hip)
+  uint64_t pair_lists = 0, pair_entries = 0;  // stored edge lists (n2v_pairs.hip)
 };
 
 extern thread_local std::string t_err;
