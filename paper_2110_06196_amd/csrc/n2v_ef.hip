@@ -375,10 +375,15 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
     uint64_t lo = ef_rank(e, (uint64_t)v << e.k);
     const uint64_t lt_mask = gl == 0 ? 0ull : (~0ull >> (64 - gl));
     auto Rv = [&](uint32_t j) -> uint64_t { return WEIGHTED ? (uint64_t)R[lo + j] : (uint64_t)j + 1ull; };
+    // lane gl holds the draw of step s1 + gl: one vector Philox evaluation
+    // every 64 steps instead of a scalar one per step
+    uint64_t rdraw = 0;
     for (uint32_t s = 1; s < a.L; ++s) {
       const uint32_t d = (uint32_t)(ef_rank(e, ((uint64_t)v + 1) << e.k) - lo);
       if (d == 0) break;
-      const uint64_t r = philox_draw(a.seed, s, wid);
+      const uint32_t sk = (s - 1u) & 63u;
+      if (sk == 0) rdraw = philox_draw(a.seed, s + (uint32_t)gl, wid);
+      const uint64_t r = wave_read_u64(rdraw, (int)sk);
       const bool stage = a.second_order && d <= kEfTile;
       uint32_t jsel = d;
       if (!a.second_order || t < 0) {

@@ -400,6 +400,10 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
       bool t_in_lds = false;
       int32_t* cur = bufA;  // N(t) when staged
       int32_t* nxt = bufB;  // N(v) being staged
+      // Draws depend on (step, walk) only: group lane gl holds the draw of
+      // step s1 + gl, all G computed together in the vector unit once every G
+      // steps, instead of one scalar Philox evaluation per step.
+      uint64_t rdraw = 0;
       for (uint32_t s = 1; s < a.L; ++s) {
         // row offset, degree and row weight sum: one 16-byte node record when
         // the graph has them, else the offsets and the row's last prefix entry
@@ -416,7 +420,9 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           d = (uint32_t)(O[v + 1] - lo);
         }
         if (d == 0) break;  // dead end
-        const uint64_t r = philox_draw(a.seed, s, wid);
+        const uint32_t sk = (s - 1u) & (uint32_t)(G - 1);
+        if (sk == 0) rdraw = philox_draw(a.seed, s + (uint32_t)gl, wid);
+        const uint64_t r = grp_bcast<G>(rdraw, (int)sk);
         auto Rv = [&](uint32_t j) -> uint64_t {
           return WEIGHTED ? (uint64_t)R[lo + j] : (uint64_t)j + 1ull;
         };
