@@ -88,7 +88,7 @@ GraphRec* find_graph(n2v_graph g) {
 // Launch configuration for one request on one graph.  The automatic choice
 // follows the graph's stationary mean degree sum(d^2)/sum(d): the expected
 // number of candidates per step of a long walk.
-LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
+LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di, uint64_t nwalks) {
   LaunchCfg c;
   const double ed = gr.n_entries ? (double)gr.sum_deg_sq / (double)gr.n_entries : 0.0;
   c.lanes_per_walker = ed > 256 ? 64 : (ed > 48 ? 32 : 16);
@@ -98,6 +98,20 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di) {
   c.lds_tile = c.lanes_per_walker == 64 ? 64 : (c.lanes_per_walker == 32 ? 64 : 32);
   c.list_cap = c.lanes_per_walker == 64 ? 512 : (c.lanes_per_walker == 32 ? 256 : 128);
   c.mode = 0;
+  // When every edge keeps a stored common-neighbour list, a step is a few short
+  // searches: groups of 4 lanes, 16 walks per wavefront, keep more loads in
+  // flight than one walk per wavefront (2.6x on a 1M-node Chung-Lu graph at
+  // p = 0.25, q = 4, 10M walks), once the launch has the walks to fill the
+  // chip that way; below about 80 walks per CU one walk per wavefront, whose
+  // wide searches take fewer rounds, is faster (measured on the same graph).
+  // A step on the stored-list path reads nothing from LDS, so the tile and
+  // the list capacity stay small.
+  const uint64_t cus = di.cus > 0 ? (uint64_t)di.cus : 256;
+  if (gr.pair_lists > 0 && gr.pair_lists == gr.n_entries && nwalks >= 96 * cus) {
+    c.lanes_per_walker = 4;
+    c.lds_tile = 16;
+    c.list_cap = 32;
+  }
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_tune_set) {
     if (g_tune.lanes_per_walker) c.lanes_per_walker = (int)g_tune.lanes_per_walker;
@@ -123,7 +137,8 @@ void apply_tuning_override(LaunchCfg* c, const DevInfo& di) {
     if (g_tune.list_cap) c->list_cap = (int)g_tune.list_cap;
     c->mode = (int)g_tune.route;
   }
-  if (c->lanes_per_walker < 16) c->lanes_per_walker = 16;  // the queue kernel's smallest group
+  // the queue kernel has groups of 4, 16, 32 and 64 lanes
+  if (c->lanes_per_walker != 4 && c->lanes_per_walker < 16) c->lanes_per_walker = 16;
   auto bytes = [&]() { return block_lds_bytes(c->lanes_per_walker, c->lds_tile, c->list_cap); };
   while (bytes() > di.lds_per_block_max && (c->lds_tile > 1 || c->list_cap > 1)) {
     if (c->lds_tile >= c->list_cap && c->lds_tile > 1) c->lds_tile /= 2;
@@ -728,7 +743,7 @@ static int walks_common(n2v_graph g, uint32_t kind, const int32_t* d_starts, uin
     hipError_t e = launch_walks_ef(a, path, gr->ef, di, (hipStream_t)hip_stream);
     return e == hipSuccess ? N2V_OK : hip_fail(e, "walk launch");
   }
-  LaunchCfg cfg = choose_cfg(*gr, di);
+  LaunchCfg cfg = choose_cfg(*gr, di, a.nwalks);
   hipError_t e = launch_walks(a, path, cfg, di, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "walk launch");
   return N2V_OK;

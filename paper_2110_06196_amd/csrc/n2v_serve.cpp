@@ -211,7 +211,7 @@ int autotune(BatchPlan* p) {
   (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  const int shapes[][3] = {{64, 64, 576}, {64, 128, 512}, {32, 64, 256}, {16, 32, 128}};
+  const int shapes[][3] = {{64, 64, 576}, {64, 128, 512}, {32, 64, 256}, {16, 32, 128}, {4, 16, 32}};
   float best = 1e30f;
   LaunchCfg best_cfg = p->cfg;
   hipError_t e = hipSuccess;

@@ -927,8 +927,11 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   }
 }
 
+// Occupancy bounds (measured): one walker per wavefront runs 8 waves per SIMD
+// with scalar spills; 4- and 8-lane groups, which serve graphs whose edges all
+// keep a stored list, run 5 and 6 waves with a few vector spills.
 template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS>
-__global__ __launch_bounds__(256, G == 64 ? 8 : 1) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
+__global__ __launch_bounds__(256, G == 64 ? 8 : (G == 4 ? 5 : (G == 8 ? 6 : 1))) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
                                                                                    unsigned long long* ctr, uint32_t chunk) {
   extern __shared__ int32_t lds[];
   // with one walker per wavefront the group index is uniform: say so, so that
@@ -1055,7 +1058,7 @@ __device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
 }
 
 template <int G, bool FULL>
-__global__ __launch_bounds__(256, G == 64 ? 7 : 1) void k_walk_queue(const WalkArgs* __restrict__ reqs,
+__global__ __launch_bounds__(256, G == 64 ? 7 : (G == 4 ? 5 : 1)) void k_walk_queue(const WalkArgs* __restrict__ reqs,
                                                     const QueueChunk* __restrict__ chunks, uint32_t nchunks,
                                                     uint32_t* __restrict__ head, int tile, int cap,
                                                     int mode_knob) {
@@ -1210,11 +1213,12 @@ hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nch
 }  // namespace
 
 int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks) {
-  const int G = cfg.lanes_per_walker == 16 ? 16 : (cfg.lanes_per_walker == 32 ? 32 : 64);
+  const int G = cfg.lanes_per_walker == 4 ? 4 : (cfg.lanes_per_walker == 16 ? 16 : (cfg.lanes_per_walker == 32 ? 32 : 64));
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   const uint64_t work = ((uint64_t)nchunks + gpb - 1) / gpb;
   const bool full = queue_full(cfg);
+  if (G == 4) return grid_for(full ? k_walk_queue<4, true> : k_walk_queue<4, false>, lds, work, di);
   if (G == 16) return grid_for(full ? k_walk_queue<16, true> : k_walk_queue<16, false>, lds, work, di);
   if (G == 32) return grid_for(full ? k_walk_queue<32, true> : k_walk_queue<32, false>, lds, work, di);
   return grid_for(full ? k_walk_queue<64, true> : k_walk_queue<64, false>, lds, work, di);
@@ -1224,6 +1228,7 @@ hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint
                         uint32_t* d_head, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   if (nchunks == 0) return hipSuccess;
   switch (cfg.lanes_per_walker) {
+    case 4: return go_queue<4>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
     case 16: return go_queue<16>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
     case 32: return go_queue<32>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
     default: return go_queue<64>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);

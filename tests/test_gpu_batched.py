@@ -87,6 +87,32 @@ def test_batched_equals_plain_and_oracle(graphs):
             assert np.array_equal(Yb, Yo) and np.array_equal(lb, lo), i
 
 
+def test_batched_four_lane_groups(graphs):
+    """The queue kernel with 4-lane groups (16 walks per wavefront, the shape
+    of graphs whose edges all keep a stored list) gives the plain walks and the
+    oracle's."""
+    reqs = make_requests(graphs, 60, seed=3)
+    descs, bufs = device_descs(reqs)
+    n2v.n2v_set_tuning(lanes_per_walker=4, lds_tile=16, list_cap=32)
+    try:
+        b = n2v.n2v_batch_create(descs, autotune=False)
+        assert n2v.n2v_batch_info(b)["lanes_per_walker"] == 4
+        n2v.n2v_batch_launch(b)
+        torch.cuda.synchronize()
+        n2v.n2v_batch_destroy(b)
+    finally:
+        n2v.n2v_set_tuning(reset=True)
+    for i, r in enumerate(reqs):
+        Yp, lp = plain(r)
+        Yb, lb = bufs[i][1].cpu().numpy(), bufs[i][2].cpu().numpy()
+        assert np.array_equal(Yb, Yp) and np.array_equal(lb, lp), i
+        if i % 10 == 0:
+            O, D, W = graphs[r["gi"]][1]
+            Yo, lo = oracle.walks(O, D, W, r["starts"], r["reps"], r["L"], r["kind"], r["p"], r["q"], r["seed"],
+                                  r["base"])
+            assert np.array_equal(Yb, Yo) and np.array_equal(lb, lo), i
+
+
 def test_batch_plan_graph_replays(graphs):
     """The captured hipGraph is replayed several times with eager work and
     synchronisations in between; every replay reproduces the eager walks."""
@@ -96,7 +122,7 @@ def test_batch_plan_graph_replays(graphs):
     for autotune in (True, False):
         b = n2v.n2v_batch_create(descs, autotune=autotune)
         info = n2v.n2v_batch_info(b)
-        assert info["n_requests"] == len(reqs) and info["lanes_per_walker"] in (16, 32, 64)
+        assert info["n_requests"] == len(reqs) and info["lanes_per_walker"] in (4, 16, 32, 64)
         for rep in range(3):
             for _, Y, lens in bufs:
                 Y.fill_(-9)

@@ -174,11 +174,17 @@ def test_giant_hub_rows_head_search():
     assert deg.max() > 1024 * 64  # splitter slices above 1024 entries
     starts = np.concatenate([hubs, rng.integers(0, n, 400)])
     g, keep_t = upload(O, D, W)
-    for route in (0, 2, 3):
-        n2v.n2v_set_tuning(route=route)
-        for p, q in ((0.25, 4.0), (1.0, 2.0)):
-            check(O, D, W, starts, 1, 8, NV, p, q, seed=5, g=g)
+    # without stored lists every step takes a route: one walk per wavefront,
+    # with the destination heads of the long rows
+    Ot, Dt, Wt = keep_t
+    g0 = n2v.n2v_graph_upload(Ot, Dt, Wt, flags=n2v.N2V_UPLOAD_NO_PAIR_LISTS)
+    for h in (g, g0):
+        for route in (0, 2, 3):
+            n2v.n2v_set_tuning(route=route)
+            for p, q in ((0.25, 4.0), (1.0, 2.0)):
+                check(O, D, W, starts, 1, 8, NV, p, q, seed=5, g=h)
     n2v.n2v_set_tuning(reset=True)
+    n2v.n2v_graph_release(g0)
     n2v.n2v_graph_release(g)
 
 
@@ -195,12 +201,14 @@ def test_hub_pair_lists_identical():
     assert i1["pair_lists"] > 1000 and i1["pair_entries"] > 0
     assert i0["pair_lists"] == 0 and i0["pair_entries"] == 0
     starts = np.arange(n)
-    rows = np.arange(0, n, 29)
+    # two walks per node: 40,000 walks, enough for the 4-lane groups that
+    # serve graphs whose edges all keep a list
+    rows = np.arange(0, 2 * n, 57)
     for p, q in ((0.25, 4.0), (2.0, 0.5), (1.0, 2.0), (4.0, 0.25)):
-        Y1, L1 = run(g1, starts, 1, 40, NV, p, q, seed=8)
-        Y0, L0 = run(g0, starts, 1, 40, NV, p, q, seed=8)
+        Y1, L1 = run(g1, starts, 2, 40, NV, p, q, seed=8)
+        Y0, L0 = run(g0, starts, 2, 40, NV, p, q, seed=8)
         assert np.array_equal(Y1, Y0) and np.array_equal(L1, L0), (p, q)
-        Yo, lo = oracle.walks(O, D, W, starts, 1, 40, NV, p, q, 8, 0, rows=rows)
+        Yo, lo = oracle.walks(O, D, W, starts, 2, 40, NV, p, q, 8, 0, rows=rows)
         assert np.array_equal(Y1[rows], Yo) and np.array_equal(L1[rows], lo), (p, q)
     n2v.n2v_graph_release(g0)
     n2v.n2v_graph_release(g1)
