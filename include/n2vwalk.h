@@ -84,7 +84,11 @@ typedef struct {
 enum { N2V_STORAGE_CSR = 0, N2V_STORAGE_EF = 1 };
 
 /* Launch tuning.  Zero fields mean "automatic".  Tuning never changes a walk:
- * every setting produces bit-identical output. */
+ * every setting produces bit-identical output.  Automatic node2vec launches
+ * use 4 lanes per walker on graphs whose edges all keep a stored
+ * common-neighbour list when the launch has at least 96 walks per compute
+ * unit, and 16 to 64 lanes (by the graph's degree spread) otherwise; batched
+ * and served launches take 4, 16, 32 or 64 (8 runs as 16). */
 typedef struct {
   uint32_t lanes_per_walker; /* node2vec (1/q != 1) path: 4, 8, 16, 32 or 64 lanes per walker */
   uint32_t lds_tile;         /* entries of the previous node's row staged in LDS per walker */
