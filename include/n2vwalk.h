@@ -320,8 +320,10 @@ int n2v_batch_destroy(n2v_batch b);
  * outlive the server).
  * n2v_request_submit: desc as above but d_starts is a HOST pointer (copied at
  * submit) and d_walks / d_lens are ignored (the server allocates the results).
- * arrival_ns is the caller's timestamp (CLOCK_MONOTONIC) for latency
- * accounting.  Errors: REJECTED if the request alone exceeds the budget.
+ * arrival_ns is the caller's timestamp (CLOCK_MONOTONIC; 0 = now) for latency
+ * accounting: an argument of its own because the descriptor is shared with the
+ * batched calls, where an arrival time means nothing.  Errors: REJECTED if the
+ * request alone exceeds the budget.
  * n2v_request_poll: N2V_PENDING until done, then N2V_OK and *out filled;
  * results stay valid until n2v_request_release.
  * ------------------------------------------------------------------------- */
@@ -333,12 +335,17 @@ typedef struct {
   uint64_t t_arrival_ns, t_admit_ns, t_start_ns, t_done_ns; /* CLOCK_MONOTONIC */
 } n2v_result_t;
 
-/* n2v_server_create: `reserved` must be NULL.  Work runs on an internal stream
- * in bounded quanta: each quantum is one launch of the persistent queue kernel
- * over chunks of every admitted request (at most quantum_us of estimated work),
- * and newly admitted requests join the next quantum.  No kernel ever waits on
- * the host. */
-int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, void* reserved,
+/* n2v_server_create: tuning fixes the launch shape of the server's queue
+ * kernel (lanes per walker, LDS tile, list capacity, route; zero fields keep
+ * the automatic value); NULL = automatic (64 lanes per walker, or the
+ * process-wide n2v_set_tuning override when one is set).  The shape never
+ * changes a walk.  Work runs on an internal stream in bounded quanta: each
+ * quantum is one launch of the persistent queue kernel over chunks of every
+ * admitted request (about eight chunks per resident walker group), and newly
+ * admitted requests join the next quantum.  No kernel ever waits on the host.
+ * Errors: INVALID_ARG (budget 0, max_slots outside [1, 65536], an invalid
+ * tuning field), HIP. */
+int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, const n2v_tuning_t* tuning,
                       n2v_server* out);
 int n2v_server_add_graph(n2v_server s, n2v_graph g);
 int n2v_request_submit(n2v_server s, const n2v_request_desc_t* desc, uint64_t arrival_ns,

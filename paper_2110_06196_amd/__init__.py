@@ -107,7 +107,7 @@ SIGNATURES = {
     "n2v_batch_launch": [_U64, _VP],
     "n2v_batch_info": [_U64, ctypes.POINTER(BatchInfo)],
     "n2v_batch_destroy": [_U64],
-    "n2v_server_create": [_U64, _U32, _VP, ctypes.POINTER(_U64)],
+    "n2v_server_create": [_U64, _U32, ctypes.POINTER(Tuning), ctypes.POINTER(_U64)],
     "n2v_server_add_graph": [_U64, _U64],
     "n2v_request_submit": [_U64, ctypes.POINTER(RequestDesc), _U64, ctypes.POINTER(_U64)],
     "n2v_request_poll": [_U64, _U64, ctypes.POINTER(Result)],
@@ -367,9 +367,14 @@ def n2v_batch_destroy(b: int) -> None:
 # ---------------------------------------------------------------------------
 # Serving
 # ---------------------------------------------------------------------------
-def n2v_server_create(hbm_budget_bytes: int, max_slots: int) -> int:
+def n2v_server_create(hbm_budget_bytes: int, max_slots: int, tuning: dict | None = None) -> int:
+    """tuning: None (automatic launch shape) or a dict of n2v_tuning_t fields
+    (lanes_per_walker, lds_tile, list_cap, route, flags) fixing the shape."""
     h = ctypes.c_uint64(0)
-    _check(lib().n2v_server_create(hbm_budget_bytes, max_slots, None, ctypes.byref(h)))
+    t = None
+    if tuning is not None:
+        t = ctypes.byref(Tuning(*(int(tuning.get(k, 0)) for k, _ in Tuning._fields_)))
+    _check(lib().n2v_server_create(hbm_budget_bytes, max_slots, t, ctypes.byref(h)))
     return h.value
 
 

@@ -128,14 +128,26 @@ LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di, uint64_t nwalks) {
   return c;
 }
 
-void apply_tuning_override(LaunchCfg* c, const DevInfo& di) {
+int check_tuning(const n2v_tuning_t& t) {
+  const uint32_t g = t.lanes_per_walker;
+  if (g != 0 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
+    return fail(N2V_ERR_INVALID_ARG, "lanes_per_walker must be 4, 8, 16, 32 or 64");
+  if (t.lds_tile > (1u << 16) || t.list_cap > (1u << 16))
+    return fail(N2V_ERR_INVALID_ARG, "lds_tile / list_cap too large");
+  if (t.route > N2V_ROUTE_MERGE) return fail(N2V_ERR_INVALID_ARG, "unknown route");
+  if (t.flags & ~(uint32_t)N2V_TUNE_GENERIC_ONLY) return fail(N2V_ERR_INVALID_ARG, "unknown flags");
+  return N2V_OK;
+}
+
+void apply_tuning_override(LaunchCfg* c, const DevInfo& di, const n2v_tuning_t* fixed) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_tune_set) return;
-    if (g_tune.lanes_per_walker) c->lanes_per_walker = (int)g_tune.lanes_per_walker;
-    if (g_tune.lds_tile) c->lds_tile = (int)g_tune.lds_tile;
-    if (g_tune.list_cap) c->list_cap = (int)g_tune.list_cap;
-    c->mode = (int)g_tune.route;
+    const n2v_tuning_t* t = fixed ? fixed : (g_tune_set ? &g_tune : nullptr);
+    if (!t) return;
+    if (t->lanes_per_walker) c->lanes_per_walker = (int)t->lanes_per_walker;
+    if (t->lds_tile) c->lds_tile = (int)t->lds_tile;
+    if (t->list_cap) c->list_cap = (int)t->list_cap;
+    c->mode = (int)t->route;
   }
   // the queue kernel has groups of 4, 16, 32 and 64 lanes
   if (c->lanes_per_walker != 4 && c->lanes_per_walker < 16) c->lanes_per_walker = 16;
@@ -708,13 +720,8 @@ int n2v_negative_samples(n2v_graph g, const int32_t* d_walks, uint64_t n_walks, 
 
 int n2v_set_tuning(const n2v_tuning_t* tuning) {
   if (tuning) {
-    const uint32_t g = tuning->lanes_per_walker;
-    if (g != 0 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
-      return fail(N2V_ERR_INVALID_ARG, "lanes_per_walker must be 4, 8, 16, 32 or 64");
-    if (tuning->lds_tile > (1u << 16) || tuning->list_cap > (1u << 16))
-      return fail(N2V_ERR_INVALID_ARG, "lds_tile / list_cap too large");
-    if (tuning->route > N2V_ROUTE_MERGE) return fail(N2V_ERR_INVALID_ARG, "unknown route");
-    if (tuning->flags & ~(uint32_t)N2V_TUNE_GENERIC_ONLY) return fail(N2V_ERR_INVALID_ARG, "unknown flags");
+    const int rc = check_tuning(*tuning);
+    if (rc != N2V_OK) return rc;
   }
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune_set = tuning != nullptr;

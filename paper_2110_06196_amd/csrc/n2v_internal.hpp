@@ -88,10 +88,16 @@ struct LaunchCfg {
   int full = 1;               // queue kernel with approximated steps and the two-pass route (0: exact routes only)
 };
 
+// Output slots a walker group of fewer than 16 lanes collects in LDS before
+// storing them (64 bytes).
+constexpr uint32_t kOutStage = 16;
+
 // LDS words per walker group of g lanes: two staging tiles of the previous
-// row, the common-neighbour list (positions, weights) and a 2g-entry merge
-// window (also the splitters of a long row).
-__host__ __device__ constexpr int group_lds_words(int tile, int cap, int g) { return 2 * tile + 2 * cap + 2 * g; }
+// row, the common-neighbour list (positions, weights), a 2g-entry merge
+// window (also the splitters of a long row) and, for g < 16, the output stage.
+__host__ __device__ constexpr int group_lds_words(int tile, int cap, int g) {
+  return 2 * tile + 2 * cap + 2 * g + (g < 16 ? (int)kOutStage : 0);
+}
 
 // LDS bytes of a 256-thread block for a launch shape.
 inline size_t block_lds_bytes(int lanes_per_walker, int tile, int cap) {

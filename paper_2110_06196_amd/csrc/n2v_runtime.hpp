@@ -36,8 +36,11 @@ int q16_of(double x, uint32_t* out);
 int current_devinfo(DevInfo* out);
 GraphRec* find_graph(n2v_graph g);
 LaunchCfg choose_cfg(const GraphRec& gr, const DevInfo& di);
-// Apply an n2v_set_tuning override (if any) to a batched / served launch shape.
-void apply_tuning_override(LaunchCfg* c, const DevInfo& di);
+// N2V_OK if every field of t is a valid setting (else INVALID_ARG with a message).
+int check_tuning(const n2v_tuning_t& t);
+// Apply a tuning to a batched / served launch shape: `fixed` when given (a
+// server's own), else the n2v_set_tuning override, if any.
+void apply_tuning_override(LaunchCfg* c, const DevInfo& di, const n2v_tuning_t* fixed = nullptr);
 int prepare_request(const GraphRec& gr, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
                     uint32_t walks_per_start, uint32_t walk_len, double p, double q, uint64_t seed,
                     uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens, uint32_t k_approx,

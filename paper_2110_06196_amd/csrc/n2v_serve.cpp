@@ -43,7 +43,8 @@ double step_cost(const GraphRec& gr, Path path) {
 
 struct Prepared {
   WalkArgs args;
-  double walk_cost;  // estimated units per walk row
+  double walk_cost;         // estimated units per walk row
+  bool full_lists = false;  // every edge of the graph keeps a stored common-neighbour list
 };
 
 int prepare_all(const n2v_request_desc_t* reqs, uint32_t n, std::vector<Prepared>* out) {
@@ -60,6 +61,7 @@ int prepare_all(const n2v_request_desc_t* reqs, uint32_t n, std::vector<Prepared
                              r.q, r.seed, r.walk_id_base, r.d_walks, r.d_lens, r.k_approx, &p.args, &path);
     if (rc != N2V_OK) return fail(rc, "request %u: %s", i, t_err.c_str());
     p.walk_cost = (double)(r.walk_len > 1 ? r.walk_len - 1 : 1) * step_cost(*gr, path);
+    p.full_lists = gr->pair_lists > 0 && gr->pair_lists == gr->n_entries;
     out->push_back(p);
   }
   return N2V_OK;
@@ -76,7 +78,10 @@ bool needs_full(const std::vector<Prepared>& reqs) {
 // Split every request into chunks of roughly `target` units (lane-path
 // chunks are whole multiples of 64 rows, so every group shape fills its
 // lanes) and order them longest-estimated-first.
-std::vector<QueueChunk> make_chunks(const std::vector<Prepared>& reqs, double target, double* total_cost) {
+// frac < 1 chunks only the first ceil(frac * n) rows of each request (an
+// autotuning sample).
+std::vector<QueueChunk> make_chunks(const std::vector<Prepared>& reqs, double target, double* total_cost,
+                                    double frac = 1.0) {
   struct C {
     QueueChunk c;
     double cost;
@@ -85,8 +90,9 @@ std::vector<QueueChunk> make_chunks(const std::vector<Prepared>& reqs, double ta
   double total = 0;
   for (uint32_t i = 0; i < reqs.size(); ++i) {
     const Prepared& p = reqs[i];
-    const uint64_t nw = p.args.nwalks;
+    uint64_t nw = p.args.nwalks;
     if (nw == 0) continue;
+    if (frac < 1.0) nw = std::max<uint64_t>(1, (uint64_t)std::ceil((double)nw * frac));
     total += p.walk_cost * (double)nw;
     uint64_t cw = (uint64_t)std::max(1.0, std::floor(target / std::max(p.walk_cost, 1e-9)));
     if (p.args.path != (uint32_t)Path::kGeneric) cw = std::max<uint64_t>(64, (cw + 63) / 64 * 64);
@@ -148,19 +154,42 @@ int upload_tables(const std::vector<Prepared>& reqs, const std::vector<QueueChun
   return N2V_OK;
 }
 
-double chunk_target(double total, const DevInfo& di) {
-  // about 32 chunks per resident walker group of a 64-lane launch
-  const double groups = (double)(di.cus > 0 ? di.cus : 256) * 16.0;
-  return std::max(total / (groups * 32.0), 1.0);
+// Walker groups of a shape resident on the whole device at once.
+double resident_groups(const LaunchCfg& c, const DevInfo& di) {
+  return (double)queue_grid_blocks(c, di, 1u << 30) * (double)(256 / c.lanes_per_walker);
 }
 
-LaunchCfg batch_default_cfg(const DevInfo& di) {
+// Chunk size (work units) giving about 16 chunks per resident walker group of
+// the launch shape: narrow shapes run many more groups at once, and a queue
+// with too few chunks for them leaves most groups idle (and a long tail).
+double chunk_target(double total, const LaunchCfg& c, const DevInfo& di) {
+  return std::max(total / (resident_groups(c, di) * 16.0), 1.0);
+}
+
+LaunchCfg shape_cfg(int lanes, int tile, int cap) {
   LaunchCfg c;
-  c.lanes_per_walker = 64;
-  c.lds_tile = 64;
-  c.list_cap = 576;
-  (void)di;
+  c.lanes_per_walker = lanes;
+  c.lds_tile = tile;
+  c.list_cap = cap;
   return c;
+}
+
+// Default launch shape of a batch: 4-lane groups when every second-order
+// request's graph keeps a stored common-neighbour list for every edge (a step
+// is then a few short searches, and 16 walks per wavefront keep more loads in
+// flight) and the batch has the walks to fill the device that way; one walk
+// per wavefront otherwise (wide groups build long lists faster).
+LaunchCfg batch_default_cfg(const std::vector<Prepared>& reqs, const DevInfo& di) {
+  uint64_t gen = 0;
+  bool lists = true;
+  for (const Prepared& r : reqs) {
+    if (r.args.path != (uint32_t)Path::kGeneric || r.args.nwalks == 0) continue;
+    gen += r.args.nwalks;
+    lists = lists && r.full_lists;
+  }
+  const uint64_t cus = di.cus > 0 ? (uint64_t)di.cus : 256;
+  if (gen > 0 && lists && gen >= 96 * cus) return shape_cfg(4, 16, 32);
+  return shape_cfg(64, 64, 576);
 }
 
 // ---------------------------------------------------------------------------
@@ -192,20 +221,15 @@ void free_plan(BatchPlan* p) {
   delete p;
 }
 
-// Time candidate launch shapes on an evenly spaced sample of the chunks.
+// Time candidate launch shapes on a sample of the batch: the first eighth of
+// every request's rows, chunked for each shape as the full batch would be
+// (16 chunks per resident group), so that a narrow shape's many groups are as
+// busy in the sample as in the real launch.
 int autotune(BatchPlan* p) {
-  const uint32_t n = (uint32_t)p->chunks.size();
-  if (n == 0) return N2V_OK;
-  const uint32_t want = std::max<uint32_t>(std::min<uint32_t>(n, 2048), n / 32);
-  std::vector<QueueChunk> sample;
-  const double stride = (double)n / (double)want;
-  for (uint32_t k = 0; k < want; ++k) sample.push_back(p->chunks[(uint32_t)(k * stride)]);
-  void* blk = nullptr;
-  WalkArgs* dr;
-  QueueChunk* dc;
-  uint32_t* dh;
-  int rc = upload_tables(p->reqs, sample, &blk, &dr, &dc, &dh);
-  if (rc != N2V_OK) return rc;
+  double total = 0;
+  for (const Prepared& r : p->reqs) total += r.walk_cost * (double)r.args.nwalks;
+  if (total <= 0) return N2V_OK;
+  constexpr double kFrac = 0.125;
   hipStream_t st;
   hipEvent_t e0, e1;
   (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -215,13 +239,18 @@ int autotune(BatchPlan* p) {
   float best = 1e30f;
   LaunchCfg best_cfg = p->cfg;
   hipError_t e = hipSuccess;
+  int rc = N2V_OK;
   for (const auto& sh : shapes) {
-    LaunchCfg c;
-    c.lanes_per_walker = sh[0];
-    c.lds_tile = sh[1];
-    c.list_cap = sh[2];
+    LaunchCfg c = shape_cfg(sh[0], sh[1], sh[2]);
     c.full = needs_full(p->reqs) ? 1 : 0;
     if (block_lds_bytes(c.lanes_per_walker, c.lds_tile, c.list_cap) > p->di.lds_per_block_max) continue;
+    const std::vector<QueueChunk> sample = make_chunks(p->reqs, chunk_target(total * kFrac, c, p->di), nullptr, kFrac);
+    void* blk = nullptr;
+    WalkArgs* dr;
+    QueueChunk* dc;
+    uint32_t* dh;
+    rc = upload_tables(p->reqs, sample, &blk, &dr, &dc, &dh);
+    if (rc != N2V_OK) break;
     float ms_min = 1e30f;
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
       e = hipEventRecord(e0, st);
@@ -232,6 +261,8 @@ int autotune(BatchPlan* p) {
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e == hipSuccess) ms_min = std::min(ms_min, ms);
     }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(blk);
     if (e != hipSuccess) break;
     if (ms_min < best) {
       best = ms_min;
@@ -241,7 +272,7 @@ int autotune(BatchPlan* p) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);
-  (void)hipFree(blk);
+  if (rc != N2V_OK) return rc;
   if (e != hipSuccess) return hip_fail(e, "autotune");
   p->cfg = best_cfg;
   return N2V_OK;
@@ -546,7 +577,10 @@ int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip
   if (rc != N2V_OK) return rc;
   double total = 0;
   for (const Prepared& r : pr) total += r.walk_cost * (double)r.args.nwalks;
-  std::vector<QueueChunk> chunks = make_chunks(pr, chunk_target(total, di), nullptr);
+  LaunchCfg cfg = batch_default_cfg(pr, di);
+  apply_tuning_override(&cfg, di);
+  cfg.full = needs_full(pr) ? 1 : 0;
+  std::vector<QueueChunk> chunks = make_chunks(pr, chunk_target(total, cfg, di), nullptr);
   if (chunks.empty()) return N2V_OK;
   if (chunks.size() > (1u << 30)) return fail(N2V_ERR_INVALID_ARG, "too many chunks");
   void* blk;
@@ -555,9 +589,6 @@ int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip
   uint32_t* dh;
   rc = upload_tables(pr, chunks, &blk, &dr, &dc, &dh);
   if (rc != N2V_OK) return rc;
-  LaunchCfg cfg = batch_default_cfg(di);
-  apply_tuning_override(&cfg, di);
-  cfg.full = needs_full(pr) ? 1 : 0;
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = launch_queue(dr, dc, (uint32_t)chunks.size(), dh, cfg, di, st);
   hipEvent_t ev;
@@ -587,17 +618,17 @@ int n2v_batch_create(const n2v_request_desc_t* reqs, uint32_t n_reqs, uint32_t f
   }
   double total = 0;
   for (const Prepared& r : p->reqs) total += r.walk_cost * (double)r.args.nwalks;
-  p->chunks = make_chunks(p->reqs, chunk_target(total, p->di), &p->est);
   for (const Prepared& r : p->reqs) p->nwalks += r.args.nwalks;
-  if (p->chunks.size() > (1u << 30)) {
-    delete p;
-    return fail(N2V_ERR_INVALID_ARG, "too many chunks");
-  }
-  p->cfg = batch_default_cfg(p->di);
+  p->cfg = batch_default_cfg(p->reqs, p->di);
   p->cfg.full = needs_full(p->reqs) ? 1 : 0;
-  rc = upload_tables(p->reqs, p->chunks, &p->block, &p->d_reqs, &p->d_chunks, &p->d_head);
-  if (rc == N2V_OK && (flags & N2V_BATCH_AUTOTUNE)) rc = autotune(p);
+  if (flags & N2V_BATCH_AUTOTUNE) rc = autotune(p);
   apply_tuning_override(&p->cfg, p->di);  // an explicit n2v_set_tuning wins
+  // the final chunking follows the chosen shape
+  if (rc == N2V_OK) {
+    p->chunks = make_chunks(p->reqs, chunk_target(total, p->cfg, p->di), &p->est);
+    if (p->chunks.size() > (1u << 30)) rc = fail(N2V_ERR_INVALID_ARG, "too many chunks");
+  }
+  if (rc == N2V_OK) rc = upload_tables(p->reqs, p->chunks, &p->block, &p->d_reqs, &p->d_chunks, &p->d_head);
   if (rc == N2V_OK && !p->chunks.empty()) {
     p->cfg.grid_blocks = queue_grid_blocks(p->cfg, p->di, (uint32_t)p->chunks.size());
     hipStream_t cs;
@@ -668,10 +699,13 @@ int n2v_batch_destroy(n2v_batch b) {
   return N2V_OK;
 }
 
-int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, void* reserved, n2v_server* out) {
+int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, const n2v_tuning_t* tuning, n2v_server* out) {
   if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
   *out = 0;
-  if (reserved) return fail(N2V_ERR_INVALID_ARG, "reserved must be NULL");
+  if (tuning) {
+    const int trc = check_tuning(*tuning);
+    if (trc != N2V_OK) return trc;
+  }
   if (max_slots == 0 || max_slots > (1u << 16)) return fail(N2V_ERR_INVALID_ARG, "max_slots must be in [1, 65536]");
   if (hbm_budget_bytes == 0) return fail(N2V_ERR_INVALID_ARG, "budget must be > 0");
   Server* s = new Server();
@@ -684,8 +718,8 @@ int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, void* reser
     return rc;
   }
   s->device = s->di.device;
-  s->cfg = batch_default_cfg(s->di);
-  apply_tuning_override(&s->cfg, s->di);
+  s->cfg = shape_cfg(64, 64, 576);
+  apply_tuning_override(&s->cfg, s->di, tuning);
   hipError_t e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMalloc(&s->d_steps, sizeof(unsigned long long) * max_slots);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) {

@@ -373,6 +373,13 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   uint32_t* const lpos = (uint32_t*)(bufB + tile);
   uint32_t* const lw = lpos + cap;
   int32_t* const win = (int32_t*)(lw + cap);
+  // Output pieces of at least 64 bytes (a line left partly written costs a
+  // whole line of write traffic when it leaves the cache): groups of 16 or
+  // more lanes hold one slot per lane and store G slots at once; narrower
+  // groups collect kOutStage slots in LDS (after the merge window) and store
+  // them together.
+  constexpr uint32_t OW = G >= 16 ? (uint32_t)G : kOutStage;
+  int32_t* const ostage = win + 2 * G;
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const RT* __restrict__ R = (const RT*)a.g.R;
@@ -391,7 +398,10 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
     int32_t ob = -1;  // output window: this lane holds slot s0 + gl
     uint32_t s0 = 0;
     if (start >= 0 && (int64_t)start < a.g.n) {
-      if (gl == 0) ob = start;
+      if (gl == 0) {
+        if constexpr (G >= 16) ob = start;
+        else ostage[0] = start;
+      }
       len = 1;
       int32_t v = start, t = -1;
       uint64_t tlo = 0;
@@ -895,11 +905,22 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
         const int32_t xsel = xq_ok ? xq : D[lo + jsel];
 
-        if ((uint32_t)gl == s % G) ob = xsel;
-        if (s % G == G - 1) {
-          row[s0 + gl] = ob;
-          s0 += G;
-          ob = -1;
+        if constexpr (G >= 16) {
+          if ((uint32_t)gl == s % G) ob = xsel;
+          if (s % G == G - 1) {
+            row[s0 + gl] = ob;
+            s0 += G;
+            ob = -1;
+          }
+        } else {
+          if (gl == 0) ostage[s % OW] = xsel;
+          if (s % OW == OW - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (uint32_t k = 0; k < OW; k += G) row[s0 + k + gl] = ostage[k + gl];
+            s0 += OW;
+          }
         }
         len = s + 1;
         t = v;
@@ -918,9 +939,19 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-    for (uint32_t s = s0; s < a.L; s += G) {
-      const uint32_t idx = s + gl;
-      if (idx < a.L) row[idx] = (s == s0 && idx < len) ? ob : -1;
+    if constexpr (G >= 16) {
+      for (uint32_t s = s0; s < a.L; s += G) {
+        const uint32_t idx = s + gl;
+        if (idx < a.L) row[idx] = (s == s0 && idx < len) ? ob : -1;
+      }
+    } else {
+      // slots [s0, len) are staged (len - s0 < OW), the rest are padding
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t s = s0; s < a.L; s += G) {
+        const uint32_t idx = s + gl;
+        if (idx < a.L) row[idx] = idx < len ? ostage[idx - s0] : -1;
+      }
     }
     if (a.lens && gl == 0) a.lens[w] = (int32_t)len;
     if (a.steps && gl == 0 && len > 1) atomicAdd(a.steps, (unsigned long long)(len - 1));

@@ -302,6 +302,18 @@ def many_graph(params: dict):
                     seed=params["seed"])
 
 
+def many_graphs(n_graphs: int = 64, threads: int = 16):
+    """Every graph of many_graph_params(), generated on host threads (numpy
+    releases the GIL in its sorts and random fills), largest first.  Returns
+    (params, [(O, D, W)] in graph order)."""
+    import concurrent.futures as cf
+    ps = many_graph_params(n_graphs)
+    order = sorted(range(len(ps)), key=lambda g: -ps[g]["n"])
+    with cf.ThreadPoolExecutor(max(1, threads)) as ex:
+        got = dict(zip(order, ex.map(lambda g: many_graph(ps[g]), order)))
+    return ps, [got[g] for g in range(len(ps))]
+
+
 def many_requests(graph_nodes, n_requests: int = 4096, seed: int = 7, max_starts: int = 10_000):
     """Request k: graph uniform, 1..max_starts start nodes drawn uniformly with
     replacement, walk length uniform in [10, 200], (p, q) uniform over

@@ -56,6 +56,12 @@ def test_argument_validation_without_device():
     bad = n2v.Tuning(16, 0, 0, 9, 0)
     assert L.n2v_set_tuning(ctypes.byref(bad)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_set_tuning(None) == n2v.N2V_OK
+    # a server's own tuning is checked like n2v_set_tuning's, before any device call
+    bad = n2v.Tuning(7, 0, 0, 0, 0)
+    assert L.n2v_server_create(1 << 20, 4, ctypes.byref(bad), ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
+    assert h.value == 0 and b"lanes_per_walker" in L.n2v_last_error()
+    bad = n2v.Tuning(16, 0, 0, 0, 8)
+    assert L.n2v_server_create(1 << 20, 4, ctypes.byref(bad), ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_walks_batched(None, 3, None) == n2v.N2V_ERR_INVALID_ARG
     # Elias-Fano graphs: argument checks come before any device call
     assert L.n2v_graph_upload_ef(None, 1, None, 0, None, 0, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG

@@ -37,7 +37,9 @@ def graphs():
         n2v.n2v_graph_release(g)
 
 
-def make_requests(graphs, n_req, seed):
+def make_requests(graphs, n_req, seed, approx=False):
+    """Random requests over the module's graphs; approx=True makes every fourth
+    request an approximated one (k in {1, 3, 8}, below the hubs' degrees)."""
     rng = np.random.default_rng(seed)
     reqs = []
     for k in range(n_req):
@@ -49,13 +51,42 @@ def make_requests(graphs, n_req, seed):
         L = int(rng.integers(1, 60))
         kind = FO if k % 5 == 0 else NV
         p, q = float(rng.choice(PQ)), float(rng.choice(PQ))
+        ka = int(rng.choice([1, 3, 8])) if approx and k % 4 == 1 else 0
         reqs.append(dict(gi=gi, g=g, starts=starts, reps=int(rng.integers(1, 3)), L=L, kind=kind, p=p, q=q,
-                         seed=1000 + k, base=int(rng.integers(0, 2**40))))
+                         seed=1000 + k, base=int(rng.integers(0, 2**40)), k_approx=ka))
     return reqs
 
 
 def plain(r):
+    if r.get("k_approx", 0):
+        S = torch.from_numpy(np.ascontiguousarray(r["starts"], dtype=np.int32)).cuda()
+        Y, lens = n2v.n2v_walks_approximated(r["g"], r["kind"], S, r["reps"], r["L"], r["p"], r["q"], r["k_approx"],
+                                             r["seed"], r["base"])
+        torch.cuda.synchronize()
+        return Y.cpu().numpy(), lens.cpu().numpy()
     return run(r["g"], r["starts"], r["reps"], r["L"], r["kind"], r["p"], r["q"], r["seed"], r["base"])
+
+
+def oracle_rows(graphs, r, rows=None):
+    """The oracle's walks of request r (all rows, or the given row indices)."""
+    O, D, W = graphs[r["gi"]][1]
+    return oracle.walks(O, D, W, r["starts"], r["reps"], r["L"], r["kind"], r["p"], r["q"], r["seed"], r["base"],
+                        rows, k_approx=r.get("k_approx", 0))
+
+
+def check_against_oracle(graphs, r, Y, lens, small=64, sample=8):
+    """Every row of a request of at most `small` walks, else `sample` evenly
+    spaced rows (first and last included), equal the oracle's."""
+    nw = Y.shape[0]
+    if nw == 0:
+        return
+    if nw <= small:
+        Yo, lo = oracle_rows(graphs, r)
+        assert np.array_equal(Y, Yo) and np.array_equal(lens, lo)
+        return
+    rows = np.unique(np.linspace(0, nw - 1, sample).astype(np.int64))
+    Yo, lo = oracle_rows(graphs, r, rows)
+    assert np.array_equal(Y[rows], Yo) and np.array_equal(lens[rows], lo)
 
 
 def device_descs(reqs):
@@ -157,19 +188,17 @@ def _fetch(res, L):
     return Y.cpu().numpy(), lens.cpu().numpy()
 
 
-@pytest.mark.parametrize("budget_mb,slots", [(4096, 64), (2, 3)])
-def test_server_mix_equals_alone(graphs, budget_mb, slots):
-    """Requests submitted while others run (continuous batching) produce the
-    walks of their plain, alone runs; a squeezed budget forces queueing."""
-    reqs = make_requests(graphs, 120, seed=3)
-    srv = n2v.n2v_server_create(budget_mb << 20, slots)
+def serve_all(graphs, reqs, budget_bytes, slots, tuning=None, pause_seed=9):
+    """Submit every request to a new server (some while others run), drain it
+    and return {k: ((walks, lens), steps, (t_arrival, t_admit, t_start, t_done))}."""
+    srv = n2v.n2v_server_create(budget_bytes, slots, tuning)
     for g, _, _ in graphs:
         n2v.n2v_server_add_graph(srv, g)
     ids, keep = {}, []
-    rng = np.random.default_rng(9)
+    rng = np.random.default_rng(pause_seed)
     for k, r in enumerate(reqs):
         d, arr = n2v.host_request(r["g"], r["kind"], r["starts"], r["reps"], r["L"], r["p"], r["q"], r["seed"],
-                                  r["base"])
+                                  r["base"], r.get("k_approx", 0))
         keep.append(arr)
         ids[k] = n2v.n2v_request_submit(srv, d, time.monotonic_ns())
         if rng.random() < 0.3:
@@ -183,12 +212,43 @@ def test_server_mix_equals_alone(graphs, budget_mb, slots):
 
     _drain(srv, ids, on_done)
     n2v.n2v_server_destroy(srv)
+    return got
+
+
+@pytest.mark.parametrize("budget_mb,slots", [(4096, 64), (2, 3)])
+def test_server_mix_equals_alone(graphs, budget_mb, slots):
+    """Requests submitted while others run (continuous batching) produce the
+    walks of their plain, alone runs and the oracle's (every row of requests of
+    up to 64 walks, 8 sampled rows of larger ones), approximated requests
+    included; a squeezed budget forces queueing."""
+    reqs = make_requests(graphs, 120, seed=3, approx=True)
+    assert any(r["k_approx"] for r in reqs)
+    got = serve_all(graphs, reqs, budget_mb << 20, slots)
     for k, r in enumerate(reqs):
         (Y, lens), steps, (ta, tad, ts, td) = got[k]
         Yp, lp = plain(r)
         assert np.array_equal(Y, Yp) and np.array_equal(lens, lp), k
+        check_against_oracle(graphs, r, Y, lens)
         assert steps == int(np.maximum(lp.astype(np.int64) - 1, 0).sum())
         assert ta <= tad <= ts <= td
+
+
+def test_server_fixed_tuning_equals_automatic(graphs):
+    """A server created with a fixed launch shape (through the tuning argument
+    of n2v_server_create) returns the walks of a server with the automatic
+    shape (NULL), and the oracle's."""
+    reqs = make_requests(graphs, 60, seed=11, approx=True)
+    auto = serve_all(graphs, reqs, 4096 << 20, 32, None)
+    for shape in (dict(lanes_per_walker=4, lds_tile=16, list_cap=32), dict(lanes_per_walker=32, lds_tile=64,
+                                                                         list_cap=256, route=n2v.N2V_ROUTE_MERGE)):
+        fixed = serve_all(graphs, reqs, 4096 << 20, 32, shape)
+        for k, r in enumerate(reqs):
+            (Ya, la), sa, _ = auto[k]
+            (Yf, lf), sf, _ = fixed[k]
+            assert np.array_equal(Ya, Yf) and np.array_equal(la, lf) and sa == sf, (shape, k)
+    for k, r in enumerate(reqs):
+        (Y, lens), _, _ = auto[k]
+        check_against_oracle(graphs, r, Y, lens)
 
 
 def test_server_rejects_and_errors(graphs):
