@@ -283,6 +283,20 @@ typedef struct {
 
 int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip_stream);
 
+/* Allocation-free form of n2v_walks_batched, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and the same walks, bit for bit.  The request table, the chunk
+ * queue and its counter live in a fixed 8 MiB device array inside the library
+ * (one per GPU, held until the process ends) instead of a per-call allocation:
+ * at most 4096 requests (more: N2V_ERR_INVALID_ARG, before any device work),
+ * and a batch whose chunk queue would not fit is cut into fewer, larger chunks
+ * (the walks do not change).  The call copies the tables on hip_stream and
+ * waits for that copy (so also for the stream's earlier work); the walk kernel
+ * itself runs asynchronously.  Every call on one GPU shares the array: calls
+ * whose kernels overlap in time (on different streams or host threads) race
+ * and must be serialised by the caller; calls on one stream are ordered. */
+int n2v_walks_batched_noalloc(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip_stream);
+
 /* Reusable batch plan: the request and chunk tables are uploaded once, the
  * launch shape (lanes per walker, LDS tile, list capacity) is chosen by timing
  * candidate shapes on a sample of the chunks (N2V_BATCH_AUTOTUNE; any shape

@@ -103,6 +103,7 @@ SIGNATURES = {
     "n2v_negative_samples": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP],
     "n2v_set_tuning": [ctypes.POINTER(Tuning)],
     "n2v_walks_batched": [ctypes.POINTER(RequestDesc), _U32, _VP],
+    "n2v_walks_batched_noalloc": [ctypes.POINTER(RequestDesc), _U32, _VP],
     "n2v_batch_create": [ctypes.POINTER(RequestDesc), _U32, _U32, ctypes.POINTER(_U64)],
     "n2v_batch_launch": [_U64, _VP],
     "n2v_batch_info": [_U64, ctypes.POINTER(BatchInfo)],
@@ -340,6 +341,13 @@ def n2v_walks_batched(reqs, stream=None) -> None:
     """reqs: list of RequestDesc (device pointers inside); one launch."""
     arr = (RequestDesc * len(reqs))(*reqs)
     _check(lib().n2v_walks_batched(arr, len(reqs), _stream(stream)))
+
+
+def n2v_walks_batched_noalloc(reqs, stream=None) -> None:
+    """As n2v_walks_batched, with the tables in the library's fixed device
+    array (no device allocation; at most 4096 requests)."""
+    arr = (RequestDesc * len(reqs))(*reqs)
+    _check(lib().n2v_walks_batched_noalloc(arr, len(reqs), _stream(stream)))
 
 
 def n2v_batch_create(reqs, autotune: bool = True) -> int:

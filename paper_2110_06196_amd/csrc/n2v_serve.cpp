@@ -559,6 +559,39 @@ void dispatcher(Server* s) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free batched launch: the request table, the chunk queue and its
+// head counter live in a file-scope device array instead of a hipMalloc'd
+// block.  Each device holds its own copy of the array; host code uses only
+// the address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(8) << 20;
+constexpr uint32_t kScratchMaxReqs = 4096;
+static_assert((size_t)kScratchMaxReqs * sizeof(WalkArgs) + 1024 < kScratchBytes / 2,
+              "request table must leave room for the chunk queue");
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;  // guards g_scratch_ptr
+std::unordered_map<int, void*> g_scratch_ptr;
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    it = g_scratch_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return N2V_OK;
+}
+
 }  // namespace
 }  // namespace n2v
 
@@ -601,6 +634,58 @@ int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip
   }
   std::lock_guard<std::mutex> lk(g_defer_mu);
   g_deferred.push_back({ev, blk});
+  return N2V_OK;
+}
+
+int n2v_walks_batched_noalloc(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip_stream) {
+  if (n_reqs > 0 && !reqs) return fail(N2V_ERR_INVALID_ARG, "reqs is NULL");
+  if (n_reqs > kScratchMaxReqs)
+    return fail(N2V_ERR_INVALID_ARG, "n_reqs %u exceeds the allocation-free limit of %u requests", n_reqs,
+                kScratchMaxReqs);
+  std::vector<Prepared> pr;
+  int rc = prepare_all(reqs, n_reqs, &pr);
+  if (rc != N2V_OK) return rc;
+  DevInfo di;
+  rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  double total = 0;
+  for (const Prepared& r : pr) total += r.walk_cost * (double)r.args.nwalks;
+  LaunchCfg cfg = batch_default_cfg(pr, di);
+  apply_tuning_override(&cfg, di);
+  cfg.full = needs_full(pr) ? 1 : 0;
+  // table layout as in upload_tables: requests | chunks | head counter
+  const size_t rb = pr.size() * sizeof(WalkArgs);
+  const size_t off_c = (rb + 255) / 256 * 256;
+  const size_t max_chunks = (kScratchBytes - off_c - 512) / sizeof(QueueChunk);
+  double target = chunk_target(total, cfg, di);
+  std::vector<QueueChunk> chunks = make_chunks(pr, target, nullptr);
+  // coarser chunks until the queue fits (only the load balance changes; at
+  // most one chunk per request in the limit, and n_reqs <= kScratchMaxReqs)
+  while (chunks.size() > max_chunks) {
+    target *= 2.0;
+    chunks = make_chunks(pr, target, nullptr);
+  }
+  if (chunks.empty()) return N2V_OK;
+  const size_t cb = chunks.size() * sizeof(QueueChunk);
+  const size_t off_h = off_c + (cb + 255) / 256 * 256;
+  const size_t bytes = off_h + 256;
+  void* base = nullptr;
+  rc = scratch_address(&base);
+  if (rc != N2V_OK) return rc;
+  std::vector<uint8_t> h(bytes, 0);  // the head counter starts at zero
+  for (size_t i = 0; i < pr.size(); ++i) std::memcpy(h.data() + i * sizeof(WalkArgs), &pr[i].args, sizeof(WalkArgs));
+  std::memcpy(h.data() + off_c, chunks.data(), cb);
+  hipStream_t st = (hipStream_t)hip_stream;
+  // stream order: the copy waits for earlier work on st (an earlier call's
+  // kernel still reading the array); the wait below makes the host buffer
+  // free to go and the tables complete before the kernel is enqueued
+  hipError_t e = hipMemcpyAsync(base, h.data(), bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "allocation-free batch tables");
+  uint8_t* b = (uint8_t*)base;
+  e = launch_queue((const WalkArgs*)b, (const QueueChunk*)(b + off_c), (uint32_t)chunks.size(), (uint32_t*)(b + off_h),
+                   cfg, di, st);
+  if (e != hipSuccess) return hip_fail(e, "allocation-free batched launch");
   return N2V_OK;
 }
 

@@ -63,6 +63,11 @@ def test_argument_validation_without_device():
     bad = n2v.Tuning(16, 0, 0, 0, 8)
     assert L.n2v_server_create(1 << 20, 4, ctypes.byref(bad), ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_walks_batched(None, 3, None) == n2v.N2V_ERR_INVALID_ARG
+    # the allocation-free batched form: NULL table and its request limit
+    assert L.n2v_walks_batched_noalloc(None, 3, None) == n2v.N2V_ERR_INVALID_ARG
+    over = (n2v.RequestDesc * 4097)()
+    assert L.n2v_walks_batched_noalloc(over, 4097, None) == n2v.N2V_ERR_INVALID_ARG
+    assert b"4096" in L.n2v_last_error()
     # Elias-Fano graphs: argument checks come before any device call
     assert L.n2v_graph_upload_ef(None, 1, None, 0, None, 0, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_graph_upload_ef(ctypes.c_void_p(8), 0, None, 0, None, 0, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
