@@ -130,10 +130,11 @@ enum {
  * t in N(v).  All lists are kept when they fit min(32 GiB, 256 bytes per
  * graph entry), else the ones with the most saved work per stored entry;
  * n2v_graph_info reports them.  They change no walk, only how fast its steps
- * run, and cost upload time (about 0.5 s per 2e7 entries of a power-law
- * graph) and the host memory to lay them out (about 60 bytes per graph entry during
- * the upload).  A graph whose lists do not fit the device or host memory left
- * is registered without them.  N2V_UPLOAD_NO_PAIR_LISTS skips them.
+ * run, and cost upload time (about 0.1 s per 2e7 entries of a power-law
+ * graph, all on the device) and temporary device memory to lay them out
+ * (about 44 bytes per graph entry, 77 when not every list fits).  A graph
+ * whose lists do not fit the device memory left is registered without them.
+ * N2V_UPLOAD_NO_PAIR_LISTS skips them.
  * Synchronous: validates on the device, builds the derived arrays on
  * hip_stream and waits for it.  Errors: INVALID_ARG, UNSORTED, NOMEM, HIP.
  * ------------------------------------------------------------------------- */

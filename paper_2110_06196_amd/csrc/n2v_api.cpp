@@ -325,10 +325,12 @@ int build_prefix(GraphRec* gr, const uint64_t* d_offsets, const uint32_t* d_weig
 
 // Stored common-neighbour lists of edges (n2v_pairs.hip), for weighted graphs
 // with 32-bit prefixes and at most kListMaxEntries entries, when measuring
-// them takes at most kListWorkCap bisection reads and device memory allows.  Every edge's list is kept
-// when all fit the budget of min(kListBudgetMax, 256 m) bytes (16 B per entry,
-// so 16 entries per graph entry); otherwise the edges with the most merge work
-// per stored entry, (d_t + d_v) / (entries + 4), are kept until it is full.
+// them takes at most kListWorkCap bisection reads and device memory allows.
+// Every edge's list is kept when all fit the budget of min(kListBudgetMax,
+// 256 m) bytes (16 B per entry, so 16 entries per graph entry); otherwise the
+// edges in decreasing order of saved merge work per stored entry,
+// (d_t + d_v) / (entries + 4), up to the first that does not fit (and every
+// empty list).  The selection and the layout run on the device.
 constexpr uint64_t kListMaxEntries = 1ull << 28;
 constexpr uint64_t kListWorkCap = 1ull << 37;
 constexpr uint64_t kListBudgetMax = 32ull << 30;
@@ -371,67 +373,60 @@ int build_edge_lists(GraphRec* gr, hipStream_t st) {
     }
     return hip_fail(e, what);
   };
-  std::vector<uint64_t> hO(n + 1);
-  std::vector<int32_t> hD(m);
-  hipError_t e = hipMemcpy(hO.data(), g.O, (n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(hD.data(), g.D, m * sizeof(int32_t), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hipf(e, "edge lists: graph");
-  auto deg = [&](uint64_t u) { return hO[u + 1] - hO[u]; };
-  auto bits = [](uint64_t x) { return (uint64_t)(64 - __builtin_clzll(x | 1)); };
-  std::vector<int32_t> src(m);  // source row of every entry
-  uint64_t work = 0;
-  for (uint64_t t = 0; t < n; ++t)
-    for (uint64_t k = hO[t]; k < hO[t + 1]; ++k) {
-      src[k] = (int32_t)t;
-      const uint64_t dt = deg(t), dv = deg((uint64_t)hD[k]);
-      work += std::min(dt, dv) * bits(std::max(dt, dv));
-    }
-  if (work > kListWorkCap) return N2V_OK;
-  uint4* d_meas;
+  // scalars: [0] build work, [1] entries of all lists, [2] kept edges, [3] kept entries
+  unsigned long long* d_sc;
   int32_t* d_src;
-  if ((e = tmp.alloc(&d_meas, m)) != hipSuccess || (e = tmp.alloc(&d_src, m)) != hipSuccess)
+  uint4* d_meas;
+  hipError_t e;
+  if ((e = tmp.alloc(&d_sc, 4)) != hipSuccess || (e = tmp.alloc(&d_src, m)) != hipSuccess)
     return hipf(e, "allocation");
-  if ((e = hipMemcpy(d_src, src.data(), m * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = launch_edge_lists_measure(g.O, g.D, d_src, m, (const uint32_t*)g.R, d_meas, st)) != hipSuccess ||
+  unsigned long long h_sc[4] = {0, 0, 0, 0};
+  if ((e = hipMemsetAsync(d_sc, 0, sizeof(h_sc), st)) != hipSuccess ||
+      (e = launch_edge_src(g.O, (int64_t)n, g.D, d_src, d_sc, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(h_sc, d_sc, sizeof(h_sc), hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
-    return hipf(e, "edge list measure");
-  std::vector<uint4> meas(m);  // {entries, position of t, listed weight, weight of t}
-  if ((e = hipMemcpy(meas.data(), d_meas, m * sizeof(uint4), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hipf(e, "edge list work");
+  if (h_sc[0] > kListWorkCap) return N2V_OK;
+  if ((e = tmp.alloc(&d_meas, m)) != hipSuccess) return hipf(e, "allocation");
+  if ((e = launch_edge_lists_measure(g.O, g.D, d_src, m, (const uint32_t*)g.R, d_meas, st)) != hipSuccess)
     return hipf(e, "edge list measure");
   // entries are addressed by 32-bit offsets: the budget stays below 2^31 of them
   const uint64_t budget = std::min<uint64_t>(kListBudgetMax, 256ull * m) / sizeof(uint4);
-  uint64_t all = 0;
-  for (uint64_t k = 0; k < m; ++k) all += meas[k].x;
-  std::vector<uint4> info(2 * m, make_uint4(0u, 0u, 0u, 0u));
-  for (uint64_t k = 0; k < m; ++k) info[2 * k].x = 0xFFFFFFFFu;
-  uint64_t total = 0, kept = 0;
-  auto keep = [&](uint64_t k) {
-    info[2 * k] = make_uint4((uint32_t)total, meas[k].x, meas[k].y, meas[k].z);
-    info[2 * k + 1] = make_uint4(meas[k].w, 0u, 0u, 0u);
-    total += meas[k].x;
-    ++kept;
-  };
-  if (all <= budget) {
-    for (uint64_t k = 0; k < m; ++k) keep(k);
-  } else {
-    std::vector<uint32_t> order(m);
-    std::iota(order.begin(), order.end(), 0u);
-    auto gain = [&](uint32_t k) { return (double)(deg((uint64_t)src[k]) + deg((uint64_t)hD[k])) / (meas[k].x + 4.0); };
-    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-      const double ga = gain(a), gb = gain(b);
-      return ga > gb || (ga == gb && a < b);
-    });
-    for (uint32_t k : order)
-      if (total + meas[k].x <= budget) keep(k);
+  uint64_t* d_cnt;
+  if ((e = tmp.alloc(&d_cnt, m)) != hipSuccess) return hipf(e, "allocation");
+  if ((e = launch_edge_counts(g.O, g.D, d_src, d_meas, m, d_cnt, nullptr, nullptr, d_sc + 1, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(h_sc, d_sc, sizeof(h_sc), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hipf(e, "edge list sizes");
+  uint8_t* d_keep = nullptr;  // null: every list is kept
+  if (h_sc[1] > budget) {
+    uint32_t *d_key, *d_idx, *d_key_s, *d_idx_s;
+    uint64_t *d_cnt_s, *d_cum;
+    if ((e = tmp.alloc(&d_keep, m)) != hipSuccess || (e = tmp.alloc(&d_key, m)) != hipSuccess ||
+        (e = tmp.alloc(&d_idx, m)) != hipSuccess || (e = tmp.alloc(&d_key_s, m)) != hipSuccess ||
+        (e = tmp.alloc(&d_idx_s, m)) != hipSuccess || (e = tmp.alloc(&d_cnt_s, m)) != hipSuccess ||
+        (e = tmp.alloc(&d_cum, m)) != hipSuccess)
+      return hipf(e, "allocation");
+    if ((e = launch_edge_counts(g.O, g.D, d_src, d_meas, m, d_cnt, d_key, d_idx, d_sc + 3, st)) != hipSuccess ||
+        (e = edge_keep_by_gain(d_key, d_idx, d_key_s, d_idx_s, d_cnt, d_cnt_s, d_cum, d_meas, m, budget, d_keep, st)) !=
+            hipSuccess ||
+        (e = hipMemsetAsync(d_sc + 2, 0, 2 * sizeof(unsigned long long), st)) != hipSuccess)
+      return hipf(e, "edge list selection");
   }
+  uint64_t *d_sz, *d_off;
   uint4* d_info = nullptr;
-  uint4* d_ent = nullptr;
+  if ((e = tmp.alloc(&d_sz, m)) != hipSuccess || (e = tmp.alloc(&d_off, m)) != hipSuccess) return hipf(e, "allocation");
   if ((e = hipMalloc((void**)&d_info, 2 * m * sizeof(uint4))) != hipSuccess) return hipf(e, "allocation");
   g.pair_info = d_info;
+  if ((e = edge_layout(d_meas, d_keep, m, d_sz, d_off, d_info, d_sc + 2, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(h_sc, d_sc, sizeof(h_sc), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hipf(e, "edge list layout");
+  const uint64_t total = h_sc[3], kept = h_sc[2];
+  uint4* d_ent = nullptr;
   if ((e = hipMalloc((void**)&d_ent, (total ? total : 1) * sizeof(uint4))) != hipSuccess) return hipf(e, "allocation");
   g.pair_ent = d_ent;
-  if ((e = hipMemcpy(d_info, info.data(), 2 * m * sizeof(uint4), hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = launch_edge_lists_fill(g.O, g.D, d_src, m, (const uint32_t*)g.R, d_info, d_ent, st)) != hipSuccess ||
+  if ((e = launch_edge_lists_fill(g.O, g.D, d_src, m, (const uint32_t*)g.R, d_info, d_ent, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return hipf(e, "edge list fill");
   gr->owned_bytes += 2 * m * sizeof(uint4) + total * sizeof(uint4);

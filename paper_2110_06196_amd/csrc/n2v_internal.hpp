@@ -161,6 +161,22 @@ hipError_t launch_dest_heads(const int32_t* D, uint64_t m, int32_t* HD, hipStrea
 // Passes of the edge-list builder (n2v_pairs.hip).
 hipError_t launch_edge_lists_measure(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m,
                                      const uint32_t* R, uint4* meas, hipStream_t st);
+// Source row of every entry; *work += sum of min(d_t, d_v) bits(max(d_t, d_v)) (zeroed by the caller).
+hipError_t launch_edge_src(const uint64_t* O, int64_t n, const int32_t* D, int32_t* src, unsigned long long* work,
+                           hipStream_t st);
+// cnt[e] = list length of edge e; *all += their sum (zeroed by the caller);
+// key / idx (when key is non-null): sort keys of saved work per entry, identity.
+hipError_t launch_edge_counts(const uint64_t* O, const int32_t* D, const int32_t* src, const uint4* meas, uint64_t m,
+                              uint64_t* cnt, uint32_t* key, uint32_t* idx, unsigned long long* all, hipStream_t st);
+// keep[e] = 1 for the edges whose lists are kept under `budget` entries, in
+// decreasing saved work per entry (empty lists always); synchronous.
+hipError_t edge_keep_by_gain(const uint32_t* key, const uint32_t* idx, uint32_t* key_s, uint32_t* idx_s,
+                             const uint64_t* cnt, uint64_t* cnt_s, uint64_t* cum, const uint4* meas, uint64_t m,
+                             uint64_t budget, uint8_t* keep, hipStream_t st);
+// Records of every edge (keep null: all kept) at the exclusive scan of the
+// kept lengths; tot[0] += kept edges, tot[1] = entries (zeroed by the caller); synchronous.
+hipError_t edge_layout(const uint4* meas, const uint8_t* keep, uint64_t m, uint64_t* sz, uint64_t* off, uint4* info,
+                       unsigned long long* tot, hipStream_t st);
 hipError_t launch_edge_lists_fill(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m,
                                   const uint32_t* R, const uint4* info, uint4* ent, hipStream_t st);
 hipError_t launch_row_prefix(const uint64_t* O, int64_t n, const uint32_t* W, void* R,

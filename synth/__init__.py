@@ -347,6 +347,8 @@ def chung_lu_device(n: int, n_edges: int, gamma: float, mean_deg: float, w_max: 
     dev = torch.device(device)
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
+    if log:
+        log("expected-degree sequence")
     w = torch.from_numpy(chung_lu_weights(n, gamma, mean_deg, w_max)).to(dev)
     cdf = torch.cumsum(w, 0)
     cdf /= cdf[-1].clone()
@@ -364,6 +366,8 @@ def chung_lu_device(n: int, n_edges: int, gamma: float, mean_deg: float, w_max: 
         keep = lo != hi
         keys.append(((lo << 32) | hi)[keep])
         del lo, hi, keep
+        if log:
+            log(f"edge samples {off + k}")
     del cdf
     key = torch.unique(torch.cat(keys))  # sorted, duplicates dropped
     del keys
@@ -384,6 +388,8 @@ def chung_lu_device(n: int, n_edges: int, gamma: float, mean_deg: float, w_max: 
     skey = (src << 32) | dst
     del dst
     skey, order = torch.sort(skey)
+    if log:
+        log("entries sorted")
     ew = ew[order]
     del order
     src = skey >> 32
