@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--big-scale", type=float, default=1.0,
                     help="big: scale of the graph (nodes, edge samples and max expected degree times this)")
     ap.add_argument("--big-runs", default="fo,n2v,approx", help="big: runs to take (fo, n2v, approx)")
+    ap.add_argument("--big-upload-flags", type=int, default=0, help="big: n2v_graph_upload flags")
     ap.add_argument("--step-costs", action="store_true",
                     help="big: histogram of the node2vec run's second-order steps by min(d_t, d_v)")
     ap.add_argument("--window", type=int, default=5, help="corpus: SkipGram / CBOW window")
@@ -1550,8 +1551,13 @@ def bench_big(args):
                                                         flush=True))
     torch.cuda.synchronize()
     print(f"[bench] graph generated in {time.time() - t0:.1f}s, m={D.numel()}", file=sys.stderr, flush=True)
-    g = n2v.n2v_graph_upload(O, D, W)
+    torch.cuda.synchronize()
+    tu = time.perf_counter()
+    g = n2v.n2v_graph_upload(O, D, W, flags=args.big_upload_flags)
+    t_upload = time.perf_counter() - tu
     info = n2v.n2v_graph_info(g)
+    print(f"[bench] upload {t_upload:.2f}s, hub sets {info['hub_sets']} (rows of degree >= "
+          f"{info['hub_min_degree']})", file=sys.stderr, flush=True)
     L = 80
     S = torch.arange(n, dtype=torch.int32, device=dev)
     Y = torch.empty((n, L), dtype=torch.int32, device=dev)
@@ -1606,6 +1612,8 @@ def bench_big(args):
                                   "undirected edge samples (gamma 2.2, max expected degree 2e6), weights U[1,255], "
                                   "one walk of 80 slots per node, seed 42",
                       "n_entries": int(D.numel()), "max_degree": info["max_degree"],
+                      "upload_s": t_upload, "upload_flags": args.big_upload_flags, "hub_sets": info["hub_sets"],
+                      "hub_min_degree": info["hub_min_degree"], "device_bytes": info["device_bytes"],
                       "stationary_mean_degree": info["sum_deg_sq"] / max(1, info["n_entries"])},
            "runs": runs, "step_costs": costs, "kernel_source_hash": kernel_source_hash()}
     if args.big_scale != 1.0:

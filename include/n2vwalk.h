@@ -79,6 +79,8 @@ typedef struct {
   uint32_t ef_quantum;     /* quantum of the Elias-Fano indexes (0 for CSR) */
   uint64_t pair_lists;     /* edges whose common-neighbour list is stored (see n2v_graph_upload) */
   uint64_t pair_entries;   /* entries of those lists (16 bytes each) */
+  uint64_t hub_sets;       /* rows that keep a membership set (see n2v_graph_upload) */
+  uint64_t hub_min_degree; /* degree from which rows may keep one (0 when none is kept) */
 } n2v_graph_info_t;
 
 enum { N2V_STORAGE_CSR = 0, N2V_STORAGE_EF = 1 };
@@ -102,10 +104,16 @@ enum {
   N2V_ROUTE_TWO_PASS = 1, /* stream the biased weights of N(v) twice (block sums, then one block) */
   N2V_ROUTE_PROBE = 2,    /* bisect every node of N(t) into N(v) to list the common neighbours */
   N2V_ROUTE_STREAM = 3,   /* stream N(v) and test each candidate against N(t) */
-  N2V_ROUTE_MERGE = 4     /* merge the two sorted rows, a window of N(t) at a time in LDS */
+  N2V_ROUTE_MERGE = 4,    /* merge the two sorted rows, a window of N(t) at a time in LDS */
+  N2V_ROUTE_HUB_SETS = 5  /* on 64-lane groups: look candidates up in the membership set of v (keys
+                             from N(t)) or of t (keys from N(v)) whenever one of them has a set;
+                             other steps as AUTO.  AUTO weighs the sets by the same estimate */
 };
 
-enum { N2V_UPLOAD_NO_PAIR_LISTS = 1u };
+enum { N2V_UPLOAD_NO_PAIR_LISTS = 1u, N2V_UPLOAD_NO_HUB_SETS = 2u };
+/* Upload flag: rows of degree >= 2^k (k in [1, 31]) may keep a membership
+ * set; without it the threshold is automatic (4096). */
+#define N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(k) ((uint32_t)((k) & 31u) << 8)
 
 enum {
   N2V_TUNE_GENERIC_ONLY = 1u  /* route every step through the G-lanes-per-walker kernel
@@ -119,7 +127,8 @@ enum {
  * d_dst[offsets[v] .. offsets[v+1]) strictly increasing (the sorted neighbour
  * set of the paper's CSR store, Methods "Succinct data structures").
  * d_weights: device uint32[n_entries], or NULL for an unweighted graph
- * (every weight 1).  flags: 0, or N2V_UPLOAD_NO_PAIR_LISTS.
+ * (every weight 1).  flags: 0, or any of N2V_UPLOAD_NO_PAIR_LISTS,
+ * N2V_UPLOAD_NO_HUB_SETS and N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(k).
  * The three arrays are BORROWED: the caller keeps them alive and unchanged
  * until n2v_graph_release.  Derived arrays (per-row inclusive weight prefix,
  * statistics) are owned by the library.
@@ -135,6 +144,15 @@ enum {
  * (about 44 bytes per graph entry, 77 when not every list fits).  A graph
  * whose lists do not fit the device memory left is registered without them.
  * N2V_UPLOAD_NO_PAIR_LISTS skips them.
+ * Graphs where some edge keeps no stored list also keep, for their longest
+ * rows (degree >= 4096, or >= 2^k with N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(k);
+ * longest first, within min(16 GiB, a quarter of the free device memory)),
+ * a membership set: one bit per node id plus a running member count every
+ * 480 ids (n / 480 * 64 bytes per row, e.g. 2.7 MB at 2e7 nodes), so that a
+ * second-order step between such a row and another classifies a candidate
+ * with one line read instead of a bisection (Methods, "Succinct data
+ * structures": rank over a bitmap).  They change no walk.
+ * N2V_UPLOAD_NO_HUB_SETS skips them.
  * Synchronous: validates on the device, builds the derived arrays on
  * hip_stream and waits for it.  Errors: INVALID_ARG, UNSORTED, NOMEM, HIP.
  * ------------------------------------------------------------------------- */

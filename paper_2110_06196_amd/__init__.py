@@ -25,7 +25,13 @@ N2V_STORAGE_CSR, N2V_STORAGE_EF = 0, 1
 N2V_FIRST_ORDER, N2V_NODE2VEC = 0, 1
 N2V_TUNE_GENERIC_ONLY = 1
 N2V_UPLOAD_NO_PAIR_LISTS = 1
+N2V_UPLOAD_NO_HUB_SETS = 2
 N2V_ROUTE_AUTO, N2V_ROUTE_TWO_PASS, N2V_ROUTE_PROBE, N2V_ROUTE_STREAM, N2V_ROUTE_MERGE = 0, 1, 2, 3, 4
+N2V_ROUTE_HUB_SETS = 5
+
+
+def N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(k: int) -> int:
+    return (k & 31) << 8
 N2V_BATCH_AUTOTUNE = 1
 
 _STATUS = {
@@ -46,7 +52,8 @@ class GraphInfo(ctypes.Structure):
                 ("sum_deg_sq", ctypes.c_uint64), ("weighted", ctypes.c_uint32),
                 ("prefix_bytes", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
                 ("storage", ctypes.c_uint32), ("ef_quantum", ctypes.c_uint32),
-                ("pair_lists", ctypes.c_uint64), ("pair_entries", ctypes.c_uint64)]
+                ("pair_lists", ctypes.c_uint64), ("pair_entries", ctypes.c_uint64),
+                ("hub_sets", ctypes.c_uint64), ("hub_min_degree", ctypes.c_uint64)]
 
 
 class EFInfo(ctypes.Structure):
@@ -170,7 +177,8 @@ def n2v_graph_upload(offsets, dst, weights=None, stream=None, flags: int = 0) ->
     """Register a CSR graph held in device tensors (uint64 / int64 offsets,
     int32 destinations, optional int32/uint32 weights viewed as uint32).
     The tensors are borrowed: keep them alive until n2v_graph_release.
-    flags: 0 or N2V_UPLOAD_NO_PAIR_LISTS."""
+    flags: 0 or any of N2V_UPLOAD_NO_PAIR_LISTS, N2V_UPLOAD_NO_HUB_SETS and
+    N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(k)."""
     if offsets.dtype == torch.int64:
         offsets = offsets.view(torch.uint64) if hasattr(torch, "uint64") else offsets
     _dev(dst, torch.int32, "dst")

@@ -134,7 +134,7 @@ int check_tuning(const n2v_tuning_t& t) {
     return fail(N2V_ERR_INVALID_ARG, "lanes_per_walker must be 4, 8, 16, 32 or 64");
   if (t.lds_tile > (1u << 16) || t.list_cap > (1u << 16))
     return fail(N2V_ERR_INVALID_ARG, "lds_tile / list_cap too large");
-  if (t.route > N2V_ROUTE_MERGE) return fail(N2V_ERR_INVALID_ARG, "unknown route");
+  if (t.route > N2V_ROUTE_HUB_SETS) return fail(N2V_ERR_INVALID_ARG, "unknown route");
   if (t.flags & ~(uint32_t)N2V_TUNE_GENERIC_ONLY) return fail(N2V_ERR_INVALID_ARG, "unknown flags");
   return N2V_OK;
 }
@@ -435,6 +435,75 @@ int build_edge_lists(GraphRec* gr, hipStream_t st) {
   return N2V_OK;
 }
 
+// Hub membership sets (see GraphDev): for the rows of degree at least
+// 2^k (k from the upload flags; automatic: kHubSetMinDegree, and only for
+// graphs where some edge keeps no stored list, since a step with a stored
+// list builds nothing), longest first, within min(kHubSetBudgetMax, a
+// quarter of the free device memory).  They change no walk.
+constexpr uint64_t kHubSetMinDegree = 4096;
+constexpr uint64_t kHubSetBudgetMax = 16ull << 30;
+
+int build_hub_sets(GraphRec* gr, uint32_t flags, hipStream_t st) {
+  GraphDev& g = gr->dev;
+  if (flags & N2V_UPLOAD_NO_HUB_SETS) return N2V_OK;
+  const uint32_t k = (flags >> 8) & 31u;
+  uint64_t min_deg = k ? (1ull << k) : kHubSetMinDegree;
+  if (!k && gr->pair_lists == gr->n_entries) return N2V_OK;
+  if (gr->max_degree < min_deg || gr->n_nodes == 0) return N2V_OK;
+  const uint64_t n = gr->n_nodes;
+  std::vector<uint64_t> hO(n + 1);
+  hipError_t e = hipMemcpy(hO.data(), g.O, (n + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hub sets: offsets");
+  std::vector<int32_t> hubs;
+  for (uint64_t v = 0; v < n; ++v)
+    if (hO[v + 1] - hO[v] >= min_deg) hubs.push_back((int32_t)v);
+  std::stable_sort(hubs.begin(), hubs.end(), [&](int32_t a, int32_t b) {
+    return hO[a + 1] - hO[a] > hO[b + 1] - hO[b];
+  });
+  const uint64_t lines = (n + kHubLineIds - 1) / kHubLineIds;
+  const uint64_t set_bytes = lines * 64;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return N2V_OK;
+  }
+  const uint64_t budget = std::min<uint64_t>(kHubSetBudgetMax, (uint64_t)free_b / 4);
+  const uint64_t keep = std::min<uint64_t>(hubs.size(), budget / set_bytes);
+  if (keep == 0) return N2V_OK;
+  hubs.resize(keep);
+  int32_t* d_hub_of = nullptr;
+  uint32_t* d_sets = nullptr;
+  int32_t* d_hubs = nullptr;
+  auto undo = [&](hipError_t err, const char* what) -> int {
+    if (d_hub_of) (void)hipFree(d_hub_of);
+    if (d_sets) (void)hipFree(d_sets);
+    if (d_hubs) (void)hipFree(d_hubs);
+    if (err == hipErrorOutOfMemory) {  // the sets change no walk: go on without them
+      (void)hipGetLastError();
+      return N2V_OK;
+    }
+    return hip_fail(err, what);
+  };
+  if ((e = hipMalloc((void**)&d_hub_of, n * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc((void**)&d_sets, keep * set_bytes)) != hipSuccess ||
+      (e = hipMalloc((void**)&d_hubs, keep * sizeof(int32_t))) != hipSuccess)
+    return undo(e, "hub sets: allocation");
+  if ((e = hipMemsetAsync(d_hub_of, 0xFF, n * sizeof(int32_t), st)) != hipSuccess ||
+      (e = hipMemsetAsync(d_sets, 0, keep * set_bytes, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(d_hubs, hubs.data(), keep * sizeof(int32_t), hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = launch_hub_sets(g.O, g.D, d_hubs, (uint32_t)keep, lines, d_sets, d_hub_of, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return undo(e, "hub sets: build");
+  (void)hipFree(d_hubs);
+  g.hub_of = d_hub_of;
+  g.hub_sets = d_sets;
+  g.hub_lines = lines;
+  g.hub_min_deg = (uint32_t)std::min<uint64_t>(min_deg, 0xFFFFFFFFull);
+  gr->hub_count = keep;
+  gr->owned_bytes += n * sizeof(int32_t) + keep * set_bytes;
+  return N2V_OK;
+}
+
 n2v_graph register_graph(GraphRec* gr) {
   std::lock_guard<std::mutex> lk(g_mu);
   gr->handle = g_next_graph++;
@@ -447,6 +516,8 @@ void free_record(GraphRec* gr) {
   if (gr->dev.NR) hipFree(const_cast<uint4*>(gr->dev.NR));
   if (gr->dev.HR) hipFree(const_cast<void*>(gr->dev.HR));
   if (gr->dev.HD) hipFree(const_cast<int32_t*>(gr->dev.HD));
+  if (gr->dev.hub_of) hipFree(const_cast<int32_t*>(gr->dev.hub_of));
+  if (gr->dev.hub_sets) hipFree(const_cast<uint32_t*>(gr->dev.hub_sets));
   free_edge_lists(gr->dev);
   if (gr->neg_guide) hipFree(gr->neg_guide);
   if (gr->ef_mem) hipFree(gr->ef_mem);
@@ -463,7 +534,7 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
                      void* hip_stream, n2v_graph* out) {
   if (!out) return fail(N2V_ERR_INVALID_ARG, "out is NULL");
   *out = 0;
-  if ((flags & ~(uint32_t)N2V_UPLOAD_NO_PAIR_LISTS) != 0)
+  if ((flags & ~(uint32_t)(N2V_UPLOAD_NO_PAIR_LISTS | N2V_UPLOAD_NO_HUB_SETS | N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(31))) != 0)
     return fail(N2V_ERR_INVALID_ARG, "flags: unknown bits 0x%x", flags);
   int rc = check_csr_args(d_offsets, n_nodes, d_dst, n_entries);
   if (rc != N2V_OK) return rc;
@@ -502,6 +573,13 @@ int n2v_graph_upload(const uint64_t* d_offsets, uint64_t n_nodes, const int32_t*
       rc = build_edge_lists(gr, st);
     } catch (const std::bad_alloc&) {  // host memory for the layout: go on without lists
       free_edge_lists(gr->dev);
+      rc = N2V_OK;
+    }
+  }
+  if (rc == N2V_OK) {
+    try {
+      rc = build_hub_sets(gr, flags, st);
+    } catch (const std::bad_alloc&) {  // host memory for the selection: go on without sets
       rc = N2V_OK;
     }
   }
@@ -634,6 +712,8 @@ int n2v_graph_info(n2v_graph g, n2v_graph_info_t* out) {
   out->ef_quantum = gr->ef_quantum;
   out->pair_lists = gr->pair_lists;
   out->pair_entries = gr->pair_entries;
+  out->hub_sets = gr->hub_count;
+  out->hub_min_degree = gr->dev.hub_min_deg;
   return N2V_OK;
 }
 

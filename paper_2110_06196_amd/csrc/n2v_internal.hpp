@@ -42,7 +42,21 @@ struct GraphDev {
   // when the graph has none.
   const uint4* pair_info = nullptr;
   const uint4* pair_ent = nullptr;
+  // Membership sets of the hubs (rows of degree at least hub_min_deg, the
+  // longest first, within a memory budget): one bit per node id, in 64-byte
+  // lines of 15 words (480 ids) plus a 16th word holding the number of
+  // members in the set's earlier lines, so one line gives both whether x is
+  // in N(h) and, if so, its position in N(h).  hub_of[v] = index of v's set,
+  // or -1.  Null when the graph has none.
+  const int32_t* hub_of = nullptr;
+  const uint32_t* hub_sets = nullptr;
+  uint64_t hub_lines = 0;    // lines per set: ceil(n / 480)
+  uint32_t hub_min_deg = 0;  // rows shorter than this have no set
+  uint32_t hub_pad = 0;
 };
+
+// Node ids per 64-byte line of a hub set.
+constexpr uint32_t kHubLineIds = 480;
 
 // Rows at which a 64-way splitter slice exceeds 1024 entries.
 constexpr uint64_t kHeadsMinDegree = 64ull * 1024;
@@ -86,6 +100,7 @@ struct LaunchCfg {
   int mode = 0;               // 0 auto, 1 two-pass streaming, 2 probe N(t), 3 stream N(v)
   int grid_blocks = 0;        // 0 = derive from occupancy
   int full = 1;               // queue kernel with approximated steps and the two-pass route (0: exact routes only)
+  int w32 = 0;                // queue kernel for weighted graphs with 32-bit prefixes only (every request's graph)
 };
 
 // Output slots a walker group of fewer than 16 lanes collects in LDS before
@@ -158,6 +173,11 @@ hipError_t launch_node_records(const uint64_t* O, int64_t n, const uint32_t* R, 
 hipError_t launch_prefix_heads(const void* R, uint32_t r_bytes, uint64_t m, void* HR, hipStream_t st);
 // HD[i] = D[32 i] for i < ceil(m / 32).
 hipError_t launch_dest_heads(const int32_t* D, uint64_t m, int32_t* HD, hipStream_t st);
+// Hub sets (zeroed by the caller): the members' bits of every hub, then the
+// per-line member counts before each line; hub_of[hubs[i]] = i (hub_of set
+// to -1 by the caller).
+hipError_t launch_hub_sets(const uint64_t* O, const int32_t* D, const int32_t* hubs, uint32_t n_hubs,
+                           uint64_t lines, uint32_t* sets, int32_t* hub_of, hipStream_t st);
 // Passes of the edge-list builder (n2v_pairs.hip).
 hipError_t launch_edge_lists_measure(const uint64_t* O, const int32_t* D, const int32_t* src, uint64_t m,
                                      const uint32_t* R, uint4* meas, hipStream_t st);

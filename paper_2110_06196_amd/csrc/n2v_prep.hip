@@ -110,7 +110,63 @@ __global__ void k_prefix_heads(const T* __restrict__ R, uint64_t nh, T* __restri
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += stride) HR[i] = R[i << 5];
 }
 
+// Hub sets.  One block per hub: every entry of the hub's row sets its bit
+// (bits of one 32-bit word may come from several lanes: atomic or).
+__global__ __launch_bounds__(256) void k_hub_bits(const uint64_t* __restrict__ O, const int32_t* __restrict__ D,
+                                                  const int32_t* __restrict__ hubs, uint64_t lines,
+                                                  uint32_t* __restrict__ sets) {
+  const int32_t h = hubs[blockIdx.x];
+  uint32_t* const set = sets + (uint64_t)blockIdx.x * lines * 16u;
+  const uint64_t a = O[h], b = O[h + 1];
+  for (uint64_t k = a + threadIdx.x; k < b; k += blockDim.x) {
+    const uint32_t x = (uint32_t)D[k];
+    const uint32_t line = x / kHubLineIds, bit = x - line * kHubLineIds;
+    atomicOr(set + (uint64_t)line * 16u + (bit >> 5), 1u << (bit & 31u));
+  }
+}
+
+// One block per hub: word 15 of every line = members in the earlier lines
+// (each thread counts a contiguous range of lines; a block scan of the
+// counts gives the range's base).
+__global__ __launch_bounds__(256) void k_hub_ranks(uint64_t lines, uint32_t* __restrict__ sets,
+                                                   const int32_t* __restrict__ hubs, int32_t* __restrict__ hub_of) {
+  __shared__ uint32_t part[256];
+  uint32_t* const set = sets + (uint64_t)blockIdx.x * lines * 16u;
+  const uint64_t per = (lines + blockDim.x - 1) / blockDim.x;
+  const uint64_t l0 = min(lines, (uint64_t)threadIdx.x * per), l1 = min(lines, l0 + per);
+  uint32_t cnt = 0;
+  for (uint64_t l = l0; l < l1; ++l)
+    for (int w = 0; w < 15; ++w) cnt += (uint32_t)__popc(set[l * 16u + (uint64_t)w]);
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  // inclusive scan of the 256 counts (Hillis-Steele)
+  for (unsigned off = 1; off < blockDim.x; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t base = part[threadIdx.x] - cnt;
+  for (uint64_t l = l0; l < l1; ++l) {
+    uint32_t c = 0;
+    for (int w = 0; w < 15; ++w) c += (uint32_t)__popc(set[l * 16u + (uint64_t)w]);
+    set[l * 16u + 15u] = base;
+    base += c;
+  }
+  if (threadIdx.x == 0) hub_of[hubs[blockIdx.x]] = (int32_t)blockIdx.x;
+}
+
 }  // namespace
+
+hipError_t launch_hub_sets(const uint64_t* O, const int32_t* D, const int32_t* hubs, uint32_t n_hubs,
+                           uint64_t lines, uint32_t* sets, int32_t* hub_of, hipStream_t st) {
+  if (n_hubs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hub_bits, dim3(n_hubs), dim3(256), 0, st, O, D, hubs, lines, sets);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hub_ranks, dim3(n_hubs), dim3(256), 0, st, lines, sets, hubs, hub_of);
+  return hipGetLastError();
+}
 
 hipError_t launch_prefix_heads(const void* R, uint32_t r_bytes, uint64_t m, void* HR, hipStream_t st) {
   const uint64_t nh = (m + 31) >> 5;

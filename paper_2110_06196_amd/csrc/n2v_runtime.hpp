@@ -27,6 +27,7 @@ struct GraphRec {
   void* ef_mem = nullptr;    // owned: H, L, S1, S0
   uint32_t ef_quantum = 0;
   uint64_t pair_lists = 0, pair_entries = 0;  // stored edge lists (n2v_pairs.hip)
+  uint64_t hub_count = 0;                     // hub membership sets (dev.hub_sets)
 };
 
 extern thread_local std::string t_err;

@@ -75,13 +75,23 @@ bool needs_full(const std::vector<Prepared>& reqs) {
   return false;
 }
 
-// Split every request into chunks of roughly `target` units (lane-path
-// chunks are whole multiples of 64 rows, so every group shape fills its
-// lanes) and order them longest-estimated-first.
+// Whether every request's graph is weighted with 32-bit prefixes (the queue
+// kernel then carries only those walk variants).
+bool weighted32(const WalkArgs& a) { return a.g.W != nullptr && a.g.r_bytes == 4; }
+int all_w32(const std::vector<Prepared>& reqs) {
+  for (const Prepared& r : reqs)
+    if (!weighted32(r.args)) return 0;
+  return 1;
+}
+
+// Split every request into chunks of roughly `target` units and order them
+// longest-estimated-first.  A wavefront runs one chunk at a time: lane-path
+// chunks are whole multiples of 64 rows (one per lane) and node2vec chunks
+// whole multiples of `unit` rows (the wavefront's walker groups).
 // frac < 1 chunks only the first ceil(frac * n) rows of each request (an
 // autotuning sample).
-std::vector<QueueChunk> make_chunks(const std::vector<Prepared>& reqs, double target, double* total_cost,
-                                    double frac = 1.0) {
+std::vector<QueueChunk> make_chunks(const std::vector<Prepared>& reqs, double target, uint64_t unit,
+                                    double* total_cost, double frac = 1.0) {
   struct C {
     QueueChunk c;
     double cost;
@@ -95,7 +105,8 @@ std::vector<QueueChunk> make_chunks(const std::vector<Prepared>& reqs, double ta
     if (frac < 1.0) nw = std::max<uint64_t>(1, (uint64_t)std::ceil((double)nw * frac));
     total += p.walk_cost * (double)nw;
     uint64_t cw = (uint64_t)std::max(1.0, std::floor(target / std::max(p.walk_cost, 1e-9)));
-    if (p.args.path != (uint32_t)Path::kGeneric) cw = std::max<uint64_t>(64, (cw + 63) / 64 * 64);
+    const uint64_t u = p.args.path != (uint32_t)Path::kGeneric ? 64 : unit;
+    cw = std::max<uint64_t>(u, (cw + u - 1) / u * u);
     for (uint64_t w0 = 0; w0 < nw; w0 += cw) {
       const uint64_t w1 = std::min(nw, w0 + cw);
       v.push_back({{i, 0, w0, w1}, p.walk_cost * (double)(w1 - w0)});
@@ -154,16 +165,18 @@ int upload_tables(const std::vector<Prepared>& reqs, const std::vector<QueueChun
   return N2V_OK;
 }
 
-// Walker groups of a shape resident on the whole device at once.
-double resident_groups(const LaunchCfg& c, const DevInfo& di) {
-  return (double)queue_grid_blocks(c, di, 1u << 30) * (double)(256 / c.lanes_per_walker);
+// Wavefronts of a shape resident on the whole device at once.
+double resident_waves(const LaunchCfg& c, const DevInfo& di) {
+  return (double)queue_grid_blocks(c, di, 1u << 30) * 4.0;
 }
 
-// Chunk size (work units) giving about 16 chunks per resident walker group of
-// the launch shape: narrow shapes run many more groups at once, and a queue
-// with too few chunks for them leaves most groups idle (and a long tail).
+// Node2vec rows per chunk unit: one per walker group of a wavefront.
+uint64_t group_unit(const LaunchCfg& c) { return (uint64_t)(64 / c.lanes_per_walker); }
+
+// Chunk size (work units) giving about 16 chunks per resident wavefront: a
+// queue with too few chunks leaves wavefronts idle (and a long tail).
 double chunk_target(double total, const LaunchCfg& c, const DevInfo& di) {
-  return std::max(total / (resident_groups(c, di) * 16.0), 1.0);
+  return std::max(total / (resident_waves(c, di) * 16.0), 1.0);
 }
 
 LaunchCfg shape_cfg(int lanes, int tile, int cap) {
@@ -243,8 +256,10 @@ int autotune(BatchPlan* p) {
   for (const auto& sh : shapes) {
     LaunchCfg c = shape_cfg(sh[0], sh[1], sh[2]);
     c.full = needs_full(p->reqs) ? 1 : 0;
+    c.w32 = all_w32(p->reqs);
     if (block_lds_bytes(c.lanes_per_walker, c.lds_tile, c.list_cap) > p->di.lds_per_block_max) continue;
-    const std::vector<QueueChunk> sample = make_chunks(p->reqs, chunk_target(total * kFrac, c, p->di), nullptr, kFrac);
+    const std::vector<QueueChunk> sample =
+        make_chunks(p->reqs, chunk_target(total * kFrac, c, p->di), group_unit(c), nullptr, kFrac);
     void* blk = nullptr;
     WalkArgs* dr;
     QueueChunk* dc;
@@ -335,7 +350,7 @@ struct Server {
   LaunchCfg cfg;
   DevInfo di;
   int device = 0;
-  size_t quantum_chunks = 0;  // chunks per quantum: eight per resident walker group
+  size_t quantum_chunks = 0;  // chunks per quantum: eight per resident wavefront
   int fatal = N2V_OK;
 };
 
@@ -390,9 +405,9 @@ void admit_locked(Server* s) {
     }
     r->args.steps = s->d_steps + r->slot;
     r->walk_cost = (double)(d.walk_len > 1 ? d.walk_len - 1 : 1) * step_cost(*r->gr, path);
-    // the finest grain each group shape can use: one walk on the node2vec
-    // path (a whole group per walk), one wave of walks on the lane paths
-    r->chunk_rows = path == Path::kGeneric ? 1 : 64;
+    // the finest grain a wavefront can use: one walk per walker group on the
+    // node2vec path, one walk per lane on the lane paths
+    r->chunk_rows = path == Path::kGeneric ? (uint64_t)(64 / s->cfg.lanes_per_walker) : 64;
     r->state = RState::kActive;
     s->active.push_back(r);
   }
@@ -401,7 +416,7 @@ void admit_locked(Server* s) {
 // Build the next quantum's chunk list (under mu): one chunk for every active
 // request with rows left (so every admitted request progresses), then more
 // chunks oldest-first until the quantum holds about eight chunks for every
-// resident walker group.
+// resident wavefront.
 void build_quantum_locked(Server* s, Quantum* q, std::vector<WalkArgs>* reqs, std::vector<QueueChunk>* chunks) {
   q->rows.clear();
   q->est = 0;
@@ -457,8 +472,11 @@ int launch_quantum(Server* s, Quantum* q, const std::vector<WalkArgs>& reqs, con
   hipError_t e = hipMemcpyAsync(q->block, q->h_stage, off_h, hipMemcpyHostToDevice, s->st);
   LaunchCfg cfg = s->cfg;
   cfg.full = 0;
-  for (const WalkArgs& r : reqs)
+  cfg.w32 = 1;
+  for (const WalkArgs& r : reqs) {
     if (r.k_approx != 0) cfg.full = 1;
+    if (!weighted32(r)) cfg.w32 = 0;
+  }
   if (e == hipSuccess)
     e = launch_queue((WalkArgs*)q->block, (QueueChunk*)((uint8_t*)q->block + off_c), (uint32_t)chunks.size(),
                      (uint32_t*)((uint8_t*)q->block + off_h), cfg, s->di, s->st);
@@ -613,7 +631,8 @@ int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip
   LaunchCfg cfg = batch_default_cfg(pr, di);
   apply_tuning_override(&cfg, di);
   cfg.full = needs_full(pr) ? 1 : 0;
-  std::vector<QueueChunk> chunks = make_chunks(pr, chunk_target(total, cfg, di), nullptr);
+  cfg.w32 = all_w32(pr);
+  std::vector<QueueChunk> chunks = make_chunks(pr, chunk_target(total, cfg, di), group_unit(cfg), nullptr);
   if (chunks.empty()) return N2V_OK;
   if (chunks.size() > (1u << 30)) return fail(N2V_ERR_INVALID_ARG, "too many chunks");
   void* blk;
@@ -653,17 +672,18 @@ int n2v_walks_batched_noalloc(const n2v_request_desc_t* reqs, uint32_t n_reqs, v
   LaunchCfg cfg = batch_default_cfg(pr, di);
   apply_tuning_override(&cfg, di);
   cfg.full = needs_full(pr) ? 1 : 0;
+  cfg.w32 = all_w32(pr);
   // table layout as in upload_tables: requests | chunks | head counter
   const size_t rb = pr.size() * sizeof(WalkArgs);
   const size_t off_c = (rb + 255) / 256 * 256;
   const size_t max_chunks = (kScratchBytes - off_c - 512) / sizeof(QueueChunk);
   double target = chunk_target(total, cfg, di);
-  std::vector<QueueChunk> chunks = make_chunks(pr, target, nullptr);
+  std::vector<QueueChunk> chunks = make_chunks(pr, target, group_unit(cfg), nullptr);
   // coarser chunks until the queue fits (only the load balance changes; at
   // most one chunk per request in the limit, and n_reqs <= kScratchMaxReqs)
   while (chunks.size() > max_chunks) {
     target *= 2.0;
-    chunks = make_chunks(pr, target, nullptr);
+    chunks = make_chunks(pr, target, group_unit(cfg), nullptr);
   }
   if (chunks.empty()) return N2V_OK;
   const size_t cb = chunks.size() * sizeof(QueueChunk);
@@ -706,11 +726,12 @@ int n2v_batch_create(const n2v_request_desc_t* reqs, uint32_t n_reqs, uint32_t f
   for (const Prepared& r : p->reqs) p->nwalks += r.args.nwalks;
   p->cfg = batch_default_cfg(p->reqs, p->di);
   p->cfg.full = needs_full(p->reqs) ? 1 : 0;
+  p->cfg.w32 = all_w32(p->reqs);
   if (flags & N2V_BATCH_AUTOTUNE) rc = autotune(p);
   apply_tuning_override(&p->cfg, p->di);  // an explicit n2v_set_tuning wins
   // the final chunking follows the chosen shape
   if (rc == N2V_OK) {
-    p->chunks = make_chunks(p->reqs, chunk_target(total, p->cfg, p->di), &p->est);
+    p->chunks = make_chunks(p->reqs, chunk_target(total, p->cfg, p->di), group_unit(p->cfg), &p->est);
     if (p->chunks.size() > (1u << 30)) rc = fail(N2V_ERR_INVALID_ARG, "too many chunks");
   }
   if (rc == N2V_OK) rc = upload_tables(p->reqs, p->chunks, &p->block, &p->d_reqs, &p->d_chunks, &p->d_head);
@@ -817,7 +838,7 @@ int n2v_server_create(uint64_t hbm_budget_bytes, uint32_t max_slots, const n2v_t
     return hip_fail(e, "server create");
   }
   s->cfg.grid_blocks = queue_grid_blocks(s->cfg, s->di, 1u << 30);
-  s->quantum_chunks = (size_t)s->cfg.grid_blocks * (256 / (size_t)s->cfg.lanes_per_walker) * 8;
+  s->quantum_chunks = (size_t)s->cfg.grid_blocks * 4 * 8;
   s->th = std::thread(dispatcher, s);
   std::lock_guard<std::mutex> lk(g_srv_mu);
   s->handle = g_next_srv++;

@@ -167,7 +167,34 @@ __device__ __forceinline__ bool global_contains(const int32_t* __restrict__ A, u
 // ---------------------------------------------------------------------------
 // node2vec kernel: G lanes per walker.
 // ---------------------------------------------------------------------------
-enum { kModeAuto = 0, kModeTwoPass = 1, kModeProbe = 2, kModeStream = 3, kModeMerge = 4 };
+enum { kModeAuto = 0, kModeTwoPass = 1, kModeProbe = 2, kModeStream = 3, kModeMerge = 4, kModeHubSets = 5,
+       kModeSetProbe = 6, kModeSetStream = 7 };
+
+// Membership of node y in a hub set (one bit, one word of the line).
+__device__ __forceinline__ bool set_member(const uint32_t* __restrict__ set, uint32_t y) {
+  const uint32_t line = y / kHubLineIds, b = y - line * kHubLineIds;
+  return (set[(uint64_t)line * 16u + (b >> 5)] >> (b & 31u)) & 1u;
+}
+
+// Membership of y in a hub set and, when it is a member, its position in the
+// hub's row: the members before it are the line's count word plus the bits
+// below y in the line (one 64-byte line read).
+__device__ __forceinline__ bool set_rank(const uint32_t* __restrict__ set, uint32_t y, uint32_t& pos) {
+  const uint32_t line = y / kHubLineIds, b = y - line * kHubLineIds;
+  const uint4* __restrict__ q = (const uint4*)(set + (uint64_t)line * 16u);
+  const uint4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+  const uint32_t w[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                          q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+  const uint32_t wi = b >> 5, bit = b & 31u;
+  uint32_t cnt = w[15], word = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 15; ++k) {
+    cnt += k < wi ? (uint32_t)__popc(w[k]) : 0u;
+    word = k == wi ? w[k] : word;
+  }
+  pos = cnt + (uint32_t)__popc(word & ((1u << bit) - 1u));
+  return (word >> bit) & 1u;
+}
 
 
 __device__ __forceinline__ uint32_t ceil_log2p1(uint32_t x) {  // ceil(log2(x + 1))
@@ -407,6 +434,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
       uint64_t tlo = 0;
       uint32_t td = 0;
       uint64_t epos = 0;  // position of the edge t -> v in N(t)
+      int32_t tset = -1;  // hub set of t, or -1
       bool t_in_lds = false;
       int32_t* cur = bufA;  // N(t) when staged
       int32_t* nxt = bufB;  // N(v) being staged
@@ -430,6 +458,10 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           d = (uint32_t)(O[v + 1] - lo);
         }
         if (d == 0) break;  // dead end
+        int32_t vset = -1;  // hub set of v, or -1
+        if constexpr (HEADS) {
+          if (a.g.hub_of != nullptr && d >= a.g.hub_min_deg) vset = a.g.hub_of[v];
+        }
         const uint32_t sk = (s - 1u) & (uint32_t)(G - 1);
         if (sk == 0) rdraw = philox_draw(a.seed, s + (uint32_t)gl, wid);
         const uint64_t r = grp_bcast<G>(rdraw, (int)sk);
@@ -646,7 +678,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           }
           if (!cached) {
             int mode = mode_knob;
-            if (mode == kModeAuto) {
+            if (mode == kModeAuto || mode == kModeHubSets) {
               // dependent-latency estimate: global load = 100, LDS load = 15
               // splitters cut a bisection of a row of n >= 4G by log2(G) global rounds for one round
               auto glob = [&](uint32_t n) -> uint32_t {
@@ -659,6 +691,24 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
               const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) * (t_in_lds ? 150u : 240u);
               mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
                                     : (stream <= merge ? kModeStream : kModeMerge);
+              if constexpr (HEADS) {
+                // a hub set answers a key with one line read: the keys of N(t)
+                // against v's set (positions included), or the candidates of
+                // N(v) against t's set
+                uint64_t best = probe < stream ? (probe < merge ? probe : merge) : (stream < merge ? stream : merge);
+                const uint64_t sprobe = (uint64_t)((td + 1 + G - 1) / G) * ((t_in_lds ? 15u : 100u) + 100u);
+                const uint64_t sstream = (uint64_t)((d + G - 1) / G) * 200u;
+                if (mode_knob == kModeHubSets) {
+                  if (vset >= 0) mode = kModeSetProbe;
+                  else if (tset >= 0) mode = kModeSetStream;
+                } else {
+                  if (vset >= 0 && sprobe < best) {
+                    best = sprobe;
+                    mode = kModeSetProbe;
+                  }
+                  if (tset >= 0 && sstream < best) mode = kModeSetStream;
+                }
+              }
             }
             if (FULL && mode == kModeTwoPass) {
               if constexpr (FULL) two_pass();
@@ -720,6 +770,50 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                     // a self-loop at t puts t in N(t): that candidate is a return, not common
                     append(hit && !tkey && y != t, pos, c);
                   }
+                } else if (HEADS && mode == kModeSetProbe) {
+                  // keys N(t) then t, as the probe route, each looked up in
+                  // v's set: membership and position from one line
+                  const uint32_t* __restrict__ vs = a.g.hub_sets + (uint64_t)vset * a.g.hub_lines * 16u;
+                  const uint32_t nk = td + 1;
+                  for (uint32_t c = from; c < nk; c += G) {
+                    if (!first && stored >= (uint32_t)cap) break;
+                    const uint32_t k = c + gl;
+                    const bool act = k < nk;
+                    const bool tkey = k == td;
+                    int32_t y = t;
+                    if (act && !tkey) y = t_in_lds ? cur[k] : D[tlo + k];
+                    uint32_t pos = 0;
+                    const bool hit = act && set_rank(vs, (uint32_t)y, pos);
+                    const uint64_t mt = grp_ballot<G>(hit && tkey, gbase);
+                    if (mt) {
+                      has_t = true;
+                      pt = (uint32_t)grp_bcast_i32<G>((int32_t)pos, __ffsll((unsigned long long)mt) - 1);
+                    }
+                    append(hit && !tkey && y != t, pos, c);
+                  }
+                } else if (HEADS && mode == kModeSetStream) {
+                  // candidates of N(v), as the stream route, each looked up in t's set
+                  const uint32_t* __restrict__ ts = a.g.hub_sets + (uint64_t)tset * a.g.hub_lines * 16u;
+                  const bool stg = first && d <= (uint32_t)tile;
+                  for (uint32_t c = from; c < d; c += G) {
+                    if (!first && stored >= (uint32_t)cap) break;
+                    const uint32_t j = c + gl;
+                    const bool act = j < d;
+                    int32_t x = 0;
+                    if (act) {
+                      x = D[lo + j];
+                      if (stg) nxt[j] = x;
+                    }
+                    const bool isret = act && x == t;
+                    const uint64_t mt = grp_ballot<G>(isret, gbase);
+                    if (mt) {
+                      has_t = true;
+                      pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
+                    }
+                    const bool in_t = act && !isret && set_member(ts, (uint32_t)x);
+                    append(in_t, j, c);
+                  }
+                  if (first) staged = stg;
                 } else if (mode == kModeMerge) {
                   // co-iterate N(v) (candidates, global) and N(t) (B): invariant
                   // "every element of B before ib is below N(v)[ia]".  A round
@@ -926,6 +1020,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         t = v;
         tlo = lo;
         td = d;
+        tset = vset;
         epos = lo + jsel;
         t_in_lds = staged;
         if (staged) {
@@ -1030,6 +1125,11 @@ struct GraphDevG {
   const N2V_GLOBAL int32_t* HD;
   const N2V_GLOBAL uint4* pair_info;
   const N2V_GLOBAL uint4* pair_ent;
+  const N2V_GLOBAL int32_t* hub_of;
+  const N2V_GLOBAL uint32_t* hub_sets;
+  uint64_t hub_lines;
+  uint32_t hub_min_deg;
+  uint32_t hub_pad;
 };
 struct WalkArgsG {
   GraphDevG g;
@@ -1051,6 +1151,8 @@ static_assert(sizeof(WalkArgsG) == sizeof(WalkArgs) && offsetof(WalkArgsG, g.NR)
                   offsetof(WalkArgsG, g.HR) == offsetof(WalkArgs, g.HR) &&
                   offsetof(WalkArgsG, g.HD) == offsetof(WalkArgs, g.HD) &&
                   offsetof(WalkArgsG, g.pair_ent) == offsetof(WalkArgs, g.pair_ent) &&
+                  offsetof(WalkArgsG, g.hub_sets) == offsetof(WalkArgs, g.hub_sets) &&
+                  offsetof(WalkArgsG, g.hub_min_deg) == offsetof(WalkArgs, g.hub_min_deg) &&
                   offsetof(WalkArgsG, starts) == offsetof(WalkArgs, starts) &&
                   offsetof(WalkArgsG, seed) == offsetof(WalkArgs, seed) && offsetof(WalkArgsG, Y) == offsetof(WalkArgs, Y) &&
                   offsetof(WalkArgsG, path) == offsetof(WalkArgs, path) &&
@@ -1071,6 +1173,10 @@ __device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
   a.g.HD = (const int32_t*)r.g.HD;
   a.g.pair_info = (const uint4*)r.g.pair_info;
   a.g.pair_ent = (const uint4*)r.g.pair_ent;
+  a.g.hub_of = (const int32_t*)r.g.hub_of;
+  a.g.hub_sets = (const uint32_t*)r.g.hub_sets;
+  a.g.hub_lines = r.g.hub_lines;
+  a.g.hub_min_deg = r.g.hub_min_deg;
   a.starts = (const int32_t*)r.starts;
   a.ns = r.ns;
   a.nwalks = r.nwalks;
@@ -1088,30 +1194,50 @@ __device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
   return a;
 }
 
-template <int G, bool FULL>
+// A wavefront pops one chunk at a time, so the request it serves is uniform
+// across the wave: the request record is read with scalar loads and lives in
+// scalar registers (with 16 groups of 4 lanes per wave, per-group requests
+// held the record in vector registers and spilled), and the wave's groups
+// run walks of one request, hence of one length.  The lanes of a lane-path
+// chunk take one walk each; the groups of a node2vec chunk take every
+// (64 / G)-th walk of it.
+// W32: every request's graph is weighted with 32-bit prefixes, so only those
+// walk variants are compiled in (fewer live registers, fewer spills).
+template <int G, bool FULL, bool W32>
 __global__ __launch_bounds__(256, G == 64 ? 7 : (G == 4 ? 5 : 1)) void k_walk_queue(const WalkArgs* __restrict__ reqs,
                                                     const QueueChunk* __restrict__ chunks, uint32_t nchunks,
                                                     uint32_t* __restrict__ head, int tile, int cap,
                                                     int mode_knob) {
   extern __shared__ int32_t lds[];
-  const int gl = (threadIdx.x & 63) & (G - 1);
+  constexpr uint32_t GPW = 64 / G;
+  const int lane = threadIdx.x & 63;
   const int gib = threadIdx.x / G;
+  const uint32_t giw = (uint32_t)lane / G;  // group index within the wavefront
   int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap, G);
   while (true) {
     uint32_t c = 0;
-    if (gl == 0) c = atomicAdd(head, 1u);
-    c = (uint32_t)grp_bcast_i32<G>((int32_t)c, 0);
-    if (c >= nchunks) break;  // every group exits once the queue is drained
+    if (lane == 0) c = atomicAdd(head, 1u);
+    c = (uint32_t)__builtin_amdgcn_readlane((int)c, 0);
+    if (c >= nchunks) break;  // every wavefront exits once the queue is drained
     const QueueChunk ch = chunks[c];
     const WalkArgs a = from_global(((const WalkArgsG*)reqs)[ch.req]);
     if (a.path != (uint32_t)Path::kGeneric) {
-      for (uint64_t w = ch.w0 + (uint64_t)gl; w < ch.w1; w += G) lane_dispatch<G>(a, w);
+      for (uint64_t w = ch.w0 + (uint64_t)lane; w < ch.w1; w += 64) {
+        if constexpr (W32) {
+          if (a.path == (uint32_t)Path::kFirstOrder) lane_walk<kFoW, uint32_t>(a, w);
+          else lane_walk<kRetW, uint32_t>(a, w);
+        } else {
+          lane_dispatch<G>(a, w);
+        }
+      }
+    } else if (W32) {
+      for (uint64_t w = ch.w0 + giw; w < ch.w1; w += GPW) group_walk<G, true, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
     } else if (a.g.W == nullptr) {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, false, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0 + giw; w < ch.w1; w += GPW) group_walk<G, false, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
     } else if (a.g.r_bytes == 8) {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint64_t, FULL>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0 + giw; w < ch.w1; w += GPW) group_walk<G, true, uint64_t, FULL>(a, w, mem, tile, cap, mode_knob);
     } else {
-      for (uint64_t w = ch.w0; w < ch.w1; ++w) group_walk<G, true, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0 + giw; w < ch.w1; w += GPW) group_walk<G, true, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
     }
   }
 }
@@ -1199,8 +1325,9 @@ hipError_t go_lane(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, h
 template <int G, bool WEIGHTED, typename RT>
 hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   const bool full = a.k_approx != 0 || cfg.mode == kModeTwoPass;
-  // 64-lane groups on graphs with destination heads take the head search
-  const bool heads = G == 64 && a.g.HD != nullptr;
+  // 64-lane groups on graphs with destination heads or hub sets take the
+  // variant that searches heads and looks keys up in the sets
+  const bool heads = G == 64 && (a.g.HD != nullptr || a.g.hub_sets != nullptr);
   auto k = full ? (heads ? k_walk_n2v<G, WEIGHTED, RT, true, G == 64> : k_walk_n2v<G, WEIGHTED, RT, true, false>)
                 : (heads ? k_walk_n2v<G, WEIGHTED, RT, false, G == 64> : k_walk_n2v<G, WEIGHTED, RT, false, false>);
   const int gpb = 256 / G;
@@ -1229,9 +1356,16 @@ hipError_t go_n2v_g(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, 
 inline bool queue_full(const LaunchCfg& cfg) { return cfg.full != 0 || cfg.mode == kModeTwoPass; }
 
 template <int G>
+auto queue_kernel(const LaunchCfg& cfg) {
+  const bool full = queue_full(cfg);
+  if (cfg.w32) return full ? k_walk_queue<G, true, true> : k_walk_queue<G, false, true>;
+  return full ? k_walk_queue<G, true, false> : k_walk_queue<G, false, false>;
+}
+
+template <int G>
 hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nchunks, uint32_t* head,
                     const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
-  auto k = queue_full(cfg) ? k_walk_queue<G, true> : k_walk_queue<G, false>;
+  auto k = queue_kernel<G>(cfg);
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, ((uint64_t)nchunks + gpb - 1) / gpb, di);
@@ -1248,11 +1382,10 @@ int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks)
   const int gpb = 256 / G;
   const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
   const uint64_t work = ((uint64_t)nchunks + gpb - 1) / gpb;
-  const bool full = queue_full(cfg);
-  if (G == 4) return grid_for(full ? k_walk_queue<4, true> : k_walk_queue<4, false>, lds, work, di);
-  if (G == 16) return grid_for(full ? k_walk_queue<16, true> : k_walk_queue<16, false>, lds, work, di);
-  if (G == 32) return grid_for(full ? k_walk_queue<32, true> : k_walk_queue<32, false>, lds, work, di);
-  return grid_for(full ? k_walk_queue<64, true> : k_walk_queue<64, false>, lds, work, di);
+  if (G == 4) return grid_for(queue_kernel<4>(cfg), lds, work, di);
+  if (G == 16) return grid_for(queue_kernel<16>(cfg), lds, work, di);
+  if (G == 32) return grid_for(queue_kernel<32>(cfg), lds, work, di);
+  return grid_for(queue_kernel<64>(cfg), lds, work, di);
 }
 
 hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint32_t nchunks,

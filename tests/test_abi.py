@@ -44,7 +44,8 @@ def test_argument_validation_without_device():
     assert h.value == 0
     assert b"offsets" in L.n2v_last_error()
     assert L.n2v_graph_upload(ctypes.c_void_p(8), 1, None, 5, None, 0, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
-    assert L.n2v_graph_upload(ctypes.c_void_p(8), 1, ctypes.c_void_p(8), 1, None, 3, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
+    assert L.n2v_graph_upload(ctypes.c_void_p(8), 1, ctypes.c_void_p(8), 1, None, 4, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
+    assert L.n2v_graph_upload(ctypes.c_void_p(8), 1, ctypes.c_void_p(8), 1, None, 1 << 13, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_graph_upload(ctypes.c_void_p(8), 2**31, ctypes.c_void_p(8), 1, None, 0, None, ctypes.byref(h)) == n2v.N2V_ERR_INVALID_ARG
     assert L.n2v_walks_first_order(12345, None, 0, 1, 1, 0, 0, None, None, None) == n2v.N2V_ERR_BAD_HANDLE
     assert L.n2v_walks_node2vec(12345, None, 0, 1, 1, 1.0, 1.0, 0, 0, None, None, None) == n2v.N2V_ERR_BAD_HANDLE

@@ -333,3 +333,62 @@ def test_first_order_skewed_prefixes(kinds):
     Yo, lo = oracle.walks(O, D, W, starts, 20, 30, FO, seed=4)
     assert np.array_equal(Y, Yo) and np.array_equal(lens, lo)
     n2v.n2v_graph_release(g)
+
+
+@pytest.mark.parametrize("weighted", [True, False])
+def test_hub_sets_identical(weighted):
+    """Membership sets of the long rows (built at upload: one bit per node and a
+    running count per 480 ids) change no walk: set lookups of N(t) into v's set
+    (positions from the counts) and of N(v) into t's set, forced whenever a
+    side has a set or weighed by the automatic estimate, give the walks of a
+    handle without sets and the oracle's."""
+    O, D, W = synth.chung_lu(20000, 200000, 2.0, 20.0, 15000.0, (1, 1000), seed=12)
+    if not weighted:
+        W = None
+    n = len(O) - 1
+    g, keep = upload(O, D, W)
+    Ot, Dt, Wt = keep
+    gs = n2v.n2v_graph_upload(Ot, Dt, Wt, flags=n2v.N2V_UPLOAD_NO_PAIR_LISTS | n2v.N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(6))
+    g0 = n2v.n2v_graph_upload(Ot, Dt, Wt, flags=n2v.N2V_UPLOAD_NO_PAIR_LISTS | n2v.N2V_UPLOAD_NO_HUB_SETS)
+    deg = (O[1:] - O[:-1]).astype(np.int64)
+    info = n2v.n2v_graph_info(gs)
+    assert info["hub_sets"] == int((deg >= 64).sum()) and info["hub_min_degree"] == 64
+    assert n2v.n2v_graph_info(g0)["hub_sets"] == 0
+    starts = np.arange(0, n, 7)
+    rows = np.arange(0, starts.size, 29)
+    for lanes, tile, route in ((64, 64, n2v.N2V_ROUTE_HUB_SETS), (64, 1, n2v.N2V_ROUTE_HUB_SETS),
+                               (64, 4096, n2v.N2V_ROUTE_AUTO), (64, 64, n2v.N2V_ROUTE_AUTO)):
+        n2v.n2v_set_tuning(lanes_per_walker=lanes, lds_tile=tile, list_cap=256, route=route)
+        for p, q in ((0.25, 4.0), (1.0, 2.0), (4.0, 0.25), (2.0, 0.5)):
+            Ys, Ls = run(gs, starts, 1, 24, NV, p, q, seed=31)
+            Y0, L0 = run(g0, starts, 1, 24, NV, p, q, seed=31)
+            assert np.array_equal(Ys, Y0) and np.array_equal(Ls, L0), (lanes, tile, route, p, q)
+            Yo, lo = oracle.walks(O, D, W, starts, 1, 24, NV, p, q, 31, 0, rows=rows)
+            assert np.array_equal(Ys[rows], Yo) and np.array_equal(Ls[rows], lo), (lanes, tile, route, p, q)
+    n2v.n2v_set_tuning(reset=True)
+    for h in (gs, g0, g):
+        n2v.n2v_graph_release(h)
+    del keep
+
+
+def test_hub_sets_directed_self_loops():
+    """Sets of out-rows of a directed graph with self-loops: a self-loop at t
+    puts t in N(t) (a return, not a common neighbour), and membership follows
+    the out-rows; walks equal the oracle's with the sets forced."""
+    rng = np.random.default_rng(3)
+    n = 3000
+    hubs = rng.integers(0, n, 8)
+    src = np.concatenate([rng.integers(0, n, 40000), np.repeat(hubs, 600), hubs])
+    dst = np.concatenate([rng.integers(0, n, 40000), rng.integers(0, n, 4800), hubs])  # self-loops at the hubs
+    O, D, W = synth.csr_from_edges(n, src, dst, rng.integers(1, 60, src.size), symmetric=False)
+    g, keep = upload(O, D, W)
+    Ot, Dt, Wt = keep
+    gs = n2v.n2v_graph_upload(Ot, Dt, Wt, flags=n2v.N2V_UPLOAD_NO_PAIR_LISTS | n2v.N2V_UPLOAD_HUB_MIN_DEGREE_LOG2(4))
+    assert n2v.n2v_graph_info(gs)["hub_sets"] > 0
+    n2v.n2v_set_tuning(lanes_per_walker=64, route=n2v.N2V_ROUTE_HUB_SETS)
+    for p, q in ((0.5, 2.0), (2.0, 0.25)):
+        check(O, D, W, np.arange(n), 1, 20, NV, p, q, seed=4, g=gs)
+    n2v.n2v_set_tuning(reset=True)
+    n2v.n2v_graph_release(gs)
+    n2v.n2v_graph_release(g)
+    del keep

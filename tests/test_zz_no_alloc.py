@@ -91,9 +91,8 @@ def check_equal(graphs, reqs, ref, got):
 
 
 def test_noalloc_equals_batched_two_calls(graphs):
-    # call 1: about 1.4e6 walks with 4-lane groups, whose queue (one chunk per
-    # second-order walk, 24 bytes each) exceeds what the fixed array holds
-    # beside the request table (about 3.5e5 chunks) and is re-cut coarser
+    # call 1: about 1.75e6 walks with 4-lane groups (a queue of tens of
+    # thousands of chunks in the fixed array)
     big = requests(graphs, 64, 40000, 8, seed=1)
     print(f"[no_alloc] call 1: {len(big)} requests, {sum(r['starts'].size * r['reps'] for r in big)} walks", flush=True)
     d_ref, b_ref = descs_and_bufs(big, -7)
