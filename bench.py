@@ -1720,6 +1720,41 @@ def bench_corpus(args):
                         "positions_per_s": npos / (ms / 1e3)})
     dom = max(kernels, key=lambda k: k["mean_ms"])
 
+    # Fused walk -> contexts (no walk array) against walks then contexts, for
+    # the corpus's walks (p = q = 1) and node2vec (0.25, 4); outputs compared
+    fused = []
+    Cf = torch.empty_like(C)
+    lf = torch.empty_like(lens)
+    Yu = torch.empty_like(Y)
+    lu = torch.empty_like(lens)
+    for p, q in ((1.0, 1.0), (0.25, 4.0)):
+        def unfused():
+            n2v.n2v_walks_node2vec(g, S, R, L, p, q, seed, 0, Yu, lu, stream=stream)
+            n2v.n2v_walk_contexts(Yu, w, 1, C, stream=stream)
+
+        def fused_op():
+            n2v.n2v_walks_contexts(g, n2v.N2V_NODE2VEC, S, R, L, p, q, seed, 0, w, 1, Cf, lf, stream=stream)
+        times = {}
+        for name, f in (("unfused", unfused), ("fused", fused_op)):
+            f()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(max(1, args.steps)):
+                f()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) / max(1, args.steps)
+        same = bool(torch.equal(C, Cf) and torch.equal(lu, lf))
+        fused.append({"p": p, "q": q, "unfused_ms": times["unfused"], "fused_ms": times["fused"], "identical": same,
+                      "unfused_device_bytes": (Yu.numel() + C.numel()) * 4, "fused_device_bytes": C.numel() * 4})
+        print(f"[bench] fused contexts (p, q) = ({p}, {q}): {times['fused']:.1f} ms, walks + contexts "
+              f"{times['unfused']:.1f} ms, identical {same}", file=sys.stderr, flush=True)
+    del Cf, Yu
+    # the contexts buffer now holds the (0.25, 4) corpus: recompute the p = q = 1 one for the oracle check
+    n2v.n2v_walk_contexts(Y, w, 1, C, stream=stream)
+    torch.cuda.synchronize()
+
     # Oracle on a contiguous block of walk rows (walk ids follow the row index).
     rows = max(1, min(nw, int(20000 * max(args.cpu_seconds, 1.0) / 15.0)))
     r0 = nw // 2 - rows // 2
@@ -1749,7 +1784,7 @@ def bench_corpus(args):
                         "kernel": dom["op"]},
            "cpu_baseline": {"value": rows * L / ct, "unit": "walk positions/s", "cores": 1, "kind": "oracle",
                             "sample": f"walk rows [{r0}, {r0 + rows}) through every corpus op ({ct:.1f} s wall)"},
-           "kernels": kernels, "parity_sample": {"rows": rows, "mismatching_rows": mism},
+           "kernels": kernels, "fused_contexts": fused, "parity_sample": {"rows": rows, "mismatching_rows": mism},
            "kernel_source_hash": kernel_source_hash(CORPUS_SOURCES)}
     print(json.dumps(out), flush=True)
     n2v.n2v_graph_release(g)

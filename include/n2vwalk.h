@@ -269,6 +269,21 @@ int n2v_walks_approximated(n2v_graph g, uint32_t kind, const int32_t* d_starts, 
  * ------------------------------------------------------------------------- */
 int n2v_walk_contexts(const int32_t* d_walks, uint64_t n_walks, uint32_t walk_len, uint32_t window,
                       uint32_t stride, int32_t* d_contexts, void* hip_stream);
+/* Fused walk -> contexts: the context slots n2v_walk_contexts would write
+ * for the walks n2v_walks_first_order (kind N2V_FIRST_ORDER; p, q ignored) or
+ * n2v_walks_node2vec (kind N2V_NODE2VEC) would produce with the same
+ * arguments, written while the walks are taken, without the walk array: each
+ * walker keeps its last 2 H + 1 positions (H = min(window * stride,
+ * walk_len - 1)) in LDS and emits the slots of position s - H once position
+ * s is drawn (and the rest when the walk ends).  d_contexts:
+ * int32[walks_per_start * n_starts][walk_len][2 window]; d_lens as in the
+ * walk calls (may be NULL).  window, stride >= 1 and H <= 1023
+ * (INVALID_ARG otherwise: materialise the walks and call
+ * n2v_walk_contexts).  Enqueued on hip_stream. */
+int n2v_walks_contexts(n2v_graph g, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
+                       uint32_t walks_per_start, uint32_t walk_len, double p, double q, uint64_t seed,
+                       uint64_t walk_id_base, uint32_t window, uint32_t stride, int32_t* d_contexts,
+                       int32_t* d_lens, void* hip_stream);
 int n2v_negative_samples(n2v_graph g, const int32_t* d_walks, uint64_t n_walks, uint32_t walk_len,
                          uint32_t n_neg, uint64_t seed, uint64_t walk_id_base, int32_t* d_negatives,
                          void* hip_stream);

@@ -107,6 +107,7 @@ SIGNATURES = {
     "n2v_ef_select": [_U64, _VP, _U64, _VP, _VP],
     "n2v_ef_rank": [_U64, _VP, _U64, _VP, _VP],
     "n2v_walk_contexts": [_VP, _U64, _U32, _U32, _U32, _VP, _VP],
+    "n2v_walks_contexts": [_U64, _U32, _VP, _U64, _U32, _U32, _D, _D, _U64, _U64, _U32, _U32, _VP, _VP, _VP],
     "n2v_negative_samples": [_U64, _VP, _U64, _U32, _U32, _U64, _U64, _VP, _VP],
     "n2v_set_tuning": [ctypes.POINTER(Tuning)],
     "n2v_walks_batched": [ctypes.POINTER(RequestDesc), _U32, _VP],
@@ -322,6 +323,27 @@ def n2v_walk_contexts(walks, window: int, stride: int = 1, contexts=None, stream
     _dev(contexts, torch.int32, "contexts")
     _check(lib().n2v_walk_contexts(_ptr(walks), nw, L, window, stride, _ptr(contexts), _stream(stream)))
     return contexts
+
+
+def n2v_walks_contexts(g: int, kind: int, starts, walks_per_start: int, walk_len: int, p: float, q: float,
+                       seed: int, walk_id_base: int, window: int, stride: int = 1, contexts=None, lens=None,
+                       stream=None):
+    """Fused walk -> contexts: the context slots [n_walks][walk_len][2 window]
+    of the walks, without the walk array; returns (contexts, lens)."""
+    _dev(starts, torch.int32, "starts")
+    nw = starts.numel() * walks_per_start
+    if contexts is None:
+        contexts = torch.empty((nw, walk_len, 2 * window), dtype=torch.int32, device=starts.device)
+    if lens is None:
+        lens = torch.empty(nw, dtype=torch.int32, device=starts.device)
+    _dev(contexts, torch.int32, "contexts")
+    _dev(lens, torch.int32, "lens")
+    if contexts.numel() != nw * walk_len * 2 * window or lens.numel() != nw:
+        raise N2VError(N2V_ERR_INVALID_ARG, "contexts / lens have the wrong size")
+    _check(lib().n2v_walks_contexts(g, kind, _ptr(starts), starts.numel(), walks_per_start, walk_len, float(p),
+                                    float(q), seed, walk_id_base, window, stride, _ptr(contexts), _ptr(lens),
+                                    _stream(stream)))
+    return contexts, lens
 
 
 def n2v_negative_samples(g: int, walks, n_neg: int, seed: int, walk_id_base: int = 0, negatives=None, stream=None):

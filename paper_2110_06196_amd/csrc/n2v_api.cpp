@@ -744,6 +744,50 @@ int n2v_walk_contexts(const int32_t* d_walks, uint64_t n_walks, uint32_t walk_le
   return e == hipSuccess ? N2V_OK : hip_fail(e, "contexts launch");
 }
 
+int n2v_walks_contexts(n2v_graph g, uint32_t kind, const int32_t* d_starts, uint64_t n_starts,
+                       uint32_t walks_per_start, uint32_t walk_len, double p, double q, uint64_t seed,
+                       uint64_t walk_id_base, uint32_t window, uint32_t stride, int32_t* d_contexts,
+                       int32_t* d_lens, void* hip_stream) {
+  GraphRec* gr = find_graph(g);
+  if (!gr) return fail(N2V_ERR_BAD_HANDLE, "unknown graph %llu", (unsigned long long)g);
+  if (gr->storage != N2V_STORAGE_CSR) return fail(N2V_ERR_INVALID_ARG, "fused contexts need a CSR graph");
+  if (window == 0 || stride == 0) return fail(N2V_ERR_INVALID_ARG, "window and stride must be >= 1");
+  if (walk_len == 0) return fail(N2V_ERR_INVALID_ARG, "walk_len must be >= 1");
+  const uint64_t hh = std::min<uint64_t>((uint64_t)window * stride, (uint64_t)walk_len - 1);
+  if (hh > kMaxFusedHalo)
+    return fail(N2V_ERR_INVALID_ARG, "window * stride %llu above the fused limit %u (materialise the walks)",
+                (unsigned long long)hh, kMaxFusedHalo);
+  if ((unsigned __int128)n_starts * walks_per_start * walk_len * window >= ((unsigned __int128)1 << 60))
+    return fail(N2V_ERR_INVALID_ARG, "output too large");
+  WalkArgs a;
+  Path path;
+  int rc = prepare_request(*gr, kind, d_starts, n_starts, walks_per_start, walk_len, p, q, seed, walk_id_base,
+                           d_contexts, d_lens, 0u, &a, &path);
+  if (rc != N2V_OK) return rc;
+  a.Y = nullptr;  // no walk array: the kernel writes contexts only
+  DevInfo di;
+  rc = current_devinfo(&di);
+  if (rc != N2V_OK) return rc;
+  uint32_t rp = 1;
+  while (rp < 2 * hh + 1) rp <<= 1;
+  LaunchCfg cfg = choose_cfg(*gr, di, a.nwalks);
+  // groups of 4, 16 or 64 lanes (the narrowest at or above the chosen width)
+  // whose block, rings included, fits the LDS
+  cfg.lanes_per_walker = cfg.lanes_per_walker <= 4 ? 4 : (cfg.lanes_per_walker <= 16 ? 16 : 64);
+  while (ctx_block_lds_bytes(cfg.lanes_per_walker, cfg.lds_tile, cfg.list_cap, rp) > di.lds_per_block_max) {
+    if (cfg.lanes_per_walker < 64) {
+      cfg.lanes_per_walker = cfg.lanes_per_walker == 4 ? 16 : 64;
+    } else if (cfg.lds_tile > 1 || cfg.list_cap > 1) {
+      if (cfg.lds_tile >= cfg.list_cap && cfg.lds_tile > 1) cfg.lds_tile /= 2;
+      else cfg.list_cap /= 2;
+    } else {
+      return fail(N2V_ERR_INVALID_ARG, "context ring of %u words does not fit the LDS", rp);
+    }
+  }
+  hipError_t e = launch_walks_ctx(a, cfg, d_contexts, window, stride, (uint32_t)hh, rp, di, (hipStream_t)hip_stream);
+  return e == hipSuccess ? N2V_OK : hip_fail(e, "fused contexts launch");
+}
+
 int n2v_negative_samples(n2v_graph g, const int32_t* d_walks, uint64_t n_walks, uint32_t walk_len,
                          uint32_t n_neg, uint64_t seed, uint64_t walk_id_base, int32_t* d_negatives,
                          void* hip_stream) {

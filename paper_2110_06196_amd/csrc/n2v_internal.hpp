@@ -157,6 +157,11 @@ hipError_t with_walk_counter(const DevInfo& di, hipStream_t st, F&& launch) {
 
 hipError_t launch_walks(const WalkArgs& a, Path path, const LaunchCfg& cfg, const DevInfo& di,
                         hipStream_t st);
+// Fused walk -> contexts (groups of 4, 16 or 64 lanes; a ring of rp words per
+// group after its region): the context slots of walk a into C.
+size_t ctx_block_lds_bytes(int lanes_per_walker, int tile, int cap, uint32_t rp);
+hipError_t launch_walks_ctx(const WalkArgs& a, const LaunchCfg& cfg, int32_t* C, uint32_t window, uint32_t stride,
+                            uint32_t h, uint32_t rp, const DevInfo& di, hipStream_t st);
 // Grid of the persistent batched kernel for this shape.
 int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks);
 // Persistent batched launch: resets *d_head (device) with a kernel, then the
@@ -234,6 +239,7 @@ hipError_t launch_contexts(const int32_t* Y, uint64_t n_walks, uint32_t L, uint3
                            int32_t* C, const DevInfo& di, hipStream_t st);
 constexpr uint32_t kMaxWindow = 1u << 16;     // context window bound (tile words stay in 32 bits)
 constexpr uint32_t kMaxNegatives = 1u << 14;  // negatives per position (one position's staging fits LDS)
+constexpr uint32_t kMaxFusedHalo = 1023;      // fused contexts: window * stride (ring of 2048 words per walker)
 
 // Negative sampling searches through a guide table of 2^shift + 1 int32
 // entries per graph (shift = neg_guide_shift(n), at most kNegGuideMaxShift).

@@ -389,9 +389,19 @@ __device__ __forceinline__ uint32_t split_floor(const int32_t* __restrict__ D, c
 // approximated step and the forced two-pass route to the exact routes; HEADS
 // the head search of long splitter slices (graphs with rows longer than
 // kHeadsMinDegree, which alone carry destination heads).
-template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS = false>
+// Fused context output (CTX): the walk's positions go to a ring of rp
+// (a power of two >= 2 h + 1) words in LDS after the group's region, and the
+// 2 window context slots of position i (the nodes at i + o stride, o = -window
+// .. -1, 1 .. window, or -1 outside the walk) are written to
+// C[row][i][*] once position i + h is drawn, or when the walk ends.
+struct CtxArgs {
+  int32_t* C = nullptr;
+  uint32_t window = 0, stride = 0, h = 0, rp = 0;
+};
+
+template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS = false, bool CTX = false>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
-                                           int mode_knob) {
+                                           int mode_knob, const CtxArgs& cx = CtxArgs{}) {
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);
@@ -407,6 +417,18 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   // them together.
   constexpr uint32_t OW = G >= 16 ? (uint32_t)G : kOutStage;
   int32_t* const ostage = win + 2 * G;
+  int32_t* const ring = mem + group_lds_words(tile, cap, G);  // CTX only
+  // context slots of position i of this walk's row; positions beyond `last`
+  // are outside the walk
+  auto emit = [&](uint32_t i, int64_t last) {
+    const uint32_t W2 = 2u * cx.window;
+    int32_t* __restrict__ out = cx.C + (w * a.L + i) * (uint64_t)W2;
+    for (uint32_t c = (uint32_t)(threadIdx.x & (G - 1)); c < W2; c += G) {
+      const int64_t o = c < cx.window ? (int64_t)c - (int64_t)cx.window : (int64_t)c - (int64_t)cx.window + 1;
+      const int64_t j = (int64_t)i + o * (int64_t)cx.stride;
+      out[c] = (j >= 0 && j <= last) ? ring[(uint32_t)j & (cx.rp - 1u)] : -1;
+    }
+  };
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const RT* __restrict__ R = (const RT*)a.g.R;
@@ -425,7 +447,11 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
     int32_t ob = -1;  // output window: this lane holds slot s0 + gl
     uint32_t s0 = 0;
     if (start >= 0 && (int64_t)start < a.g.n) {
-      if (gl == 0) {
+      if constexpr (CTX) {
+        if (gl == 0) ring[0] = start;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else if (gl == 0) {
         if constexpr (G >= 16) ob = start;
         else ostage[0] = start;
       }
@@ -999,7 +1025,12 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         if (stop || jsel >= d) break;  // total weight zero (jsel >= d is unreachable)
         const int32_t xsel = xq_ok ? xq : D[lo + jsel];
 
-        if constexpr (G >= 16) {
+        if constexpr (CTX) {
+          if (gl == 0) ring[s & (cx.rp - 1u)] = xsel;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (s >= cx.h) emit(s - cx.h, (int64_t)s);
+        } else if constexpr (G >= 16) {
           if ((uint32_t)gl == s % G) ob = xsel;
           if (s % G == G - 1) {
             row[s0 + gl] = ob;
@@ -1034,7 +1065,18 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-    if constexpr (G >= 16) {
+    if constexpr (CTX) {
+      // positions whose right neighbours ran past the end (the drawn steps
+      // emitted positions [max(h, 1) - h, len - 1 - h]; with h = 0, that is a
+      // one-slot walk, the start is left), then the padding
+      const uint32_t first = len > cx.h ? len - cx.h : 0u;
+      for (uint32_t i = first; i < len; ++i) emit(i, (int64_t)len - 1);
+      if (cx.h == 0 && len > 0) emit(0u, 0);
+      const uint32_t W2 = 2u * cx.window;
+      int32_t* __restrict__ pad = cx.C + (w * a.L + len) * (uint64_t)W2;
+      const uint64_t words = (uint64_t)(a.L - len) * W2;
+      for (uint64_t u = (uint64_t)gl; u < words; u += G) pad[u] = -1;
+    } else if constexpr (G >= 16) {
       for (uint32_t s = s0; s < a.L; s += G) {
         const uint32_t idx = s + gl;
         if (idx < a.L) row[idx] = (s == s0 && idx < len) ? ob : -1;
@@ -1081,6 +1123,34 @@ __global__ __launch_bounds__(256, G == 64 ? 8 : (G == 4 ? 5 : (G == 8 ? 6 : 1)))
     }
     if (w >= a.nwalks) break;
     group_walk<G, WEIGHTED, RT, FULL, HEADS>(a, w, mem, tile, cap, mode_knob);
+    w += ctr ? 1 : ngroups;
+  }
+}
+
+// Fused walk -> contexts: the node2vec kernel's walker loop with context
+// output (every kind runs through the group routine: its first-order branch
+// serves first-order walks and the first step of node2vec walks).
+template <int G, bool WEIGHTED, typename RT>
+__global__ __launch_bounds__(256) void k_walk_ctx(WalkArgs a, int tile, int cap, CtxArgs cx, unsigned long long* ctr,
+                                                  uint32_t chunk) {
+  extern __shared__ int32_t lds[];
+  const int gib = G == 64 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64u) : (int)(threadIdx.x / G);
+  const int gpb = blockDim.x / G;
+  int32_t* const mem = lds + (size_t)gib * (group_lds_words(tile, cap, G) + cx.rp);
+  const int gl = (threadIdx.x & 63) & (G - 1);
+  const uint64_t ngroups = (uint64_t)gridDim.x * gpb;
+  uint64_t w = ctr ? 0 : (uint64_t)blockIdx.x * gpb + gib, e = 0;
+  while (true) {
+    if (ctr) {
+      if (w >= e) {
+        unsigned long long c = 0;
+        if (gl == 0) c = atomicAdd(ctr, (unsigned long long)chunk);
+        w = grp_bcast<G>((uint64_t)c, 0);
+        e = min(w + chunk, a.nwalks);
+      }
+    }
+    if (w >= a.nwalks) break;
+    group_walk<G, WEIGHTED, RT, false, false, true>(a, w, mem, tile, cap, kModeAuto, cx);
     w += ctr ? 1 : ngroups;
   }
 }
@@ -1396,6 +1466,47 @@ hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint
     case 16: return go_queue<16>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
     case 32: return go_queue<32>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
     default: return go_queue<64>(d_reqs, d_chunks, nchunks, d_head, cfg, di, st);
+  }
+}
+
+namespace {
+template <int G, bool WEIGHTED, typename RT>
+hipError_t go_ctx(const WalkArgs& a, const LaunchCfg& cfg, const CtxArgs& cx, const DevInfo& di, hipStream_t st) {
+  auto k = k_walk_ctx<G, WEIGHTED, RT>;
+  const int gpb = 256 / G;
+  const size_t lds = (size_t)gpb * (group_lds_words(cfg.lds_tile, cfg.list_cap, G) + cx.rp) * sizeof(int32_t);
+  int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
+  return with_walk_counter(di, st, [&](unsigned long long* ctr) {
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cx, ctr,
+                       walk_chunk(a.nwalks, (uint64_t)blocks * gpb));
+    return hipGetLastError();
+  });
+}
+
+template <int G>
+hipError_t go_ctx_g(const WalkArgs& a, const LaunchCfg& cfg, const CtxArgs& cx, const DevInfo& di, hipStream_t st) {
+  if (a.g.W == nullptr) return go_ctx<G, false, uint32_t>(a, cfg, cx, di, st);
+  return a.g.r_bytes == 8 ? go_ctx<G, true, uint64_t>(a, cfg, cx, di, st) : go_ctx<G, true, uint32_t>(a, cfg, cx, di, st);
+}
+}  // namespace
+
+size_t ctx_block_lds_bytes(int lanes_per_walker, int tile, int cap, uint32_t rp) {
+  return (size_t)(256 / lanes_per_walker) * ((size_t)group_lds_words(tile, cap, lanes_per_walker) + rp) * 4;
+}
+
+hipError_t launch_walks_ctx(const WalkArgs& a, const LaunchCfg& cfg, int32_t* C, uint32_t window, uint32_t stride,
+                            uint32_t h, uint32_t rp, const DevInfo& di, hipStream_t st) {
+  if (a.nwalks == 0) return hipSuccess;
+  CtxArgs cx;
+  cx.C = C;
+  cx.window = window;
+  cx.stride = stride;
+  cx.h = h;
+  cx.rp = rp;
+  switch (cfg.lanes_per_walker) {
+    case 4: return go_ctx_g<4>(a, cfg, cx, di, st);
+    case 16: return go_ctx_g<16>(a, cfg, cx, di, st);
+    default: return go_ctx_g<64>(a, cfg, cx, di, st);
   }
 }
 
