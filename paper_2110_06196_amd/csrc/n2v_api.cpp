@@ -870,6 +870,7 @@ static int walks_common(n2v_graph g, uint32_t kind, const int32_t* d_starts, uin
     return e == hipSuccess ? N2V_OK : hip_fail(e, "walk launch");
   }
   LaunchCfg cfg = choose_cfg(*gr, di, a.nwalks);
+  cfg.lists = gr->pair_lists > 0 && gr->pair_lists == gr->n_entries ? 1 : 0;
   hipError_t e = launch_walks(a, path, cfg, di, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "walk launch");
   return N2V_OK;

@@ -83,73 +83,80 @@ __device__ __forceinline__ uint64_t ef_select(const EFDev& e, uint64_t i) {
   return ((ef_one_pos(e, i) - i) << e.l) | ef_low(e, i);
 }
 
+// The codes with high part hx: index i of the first one, and (when c is not
+// null) how many.  Their ones follow zero number hx - 1 (or start H when
+// hx = 0) and run up to zero number hx; the run is measured a 64-byte line
+// of H (8 words, loaded together) at a time.
+__device__ __forceinline__ void ef_bucket(const EFDev& e, uint64_t hx, uint64_t* i, uint64_t* c) {
+  uint64_t q = 0;
+  *i = 0;
+  if (hx > 0) {
+    const uint64_t p0 = ef_zero_pos(e, hx - 1);
+    *i = p0 - (hx - 1);
+    q = p0 + 1;
+  }
+  if (!c) return;
+  uint64_t n = 0;
+  while (q < e.h_bits) {
+    const uint32_t s = (uint32_t)(q & 63);
+    const uint64_t rem = e.H[q >> 6] >> s;
+    const uint32_t left = 64u - s;
+    const uint64_t full = left == 64u ? ~0ull : ((1ull << left) - 1);
+    if (rem == full) {
+      n += left;
+      q += left;
+      continue;
+    }
+    n += (uint64_t)__builtin_ctzll(~rem);
+    break;
+  }
+  *c = n;
+}
+
+// First index in [i, i + c) of the bucket whose low part is >= xl (low parts
+// increase inside a bucket), or i + c: a bisection over the packed low parts.
+__device__ __forceinline__ uint64_t ef_low_bound(const EFDev& e, uint64_t i, uint64_t c, uint64_t xl) {
+  uint64_t lo = i, hi = i + c;
+  while (lo < hi) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (ef_low(e, mid) < xl) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // rank(x): codes strictly below x.  Codes with high part below hx = x >> l
-// are the ones before zero number hx - 1; those with high part hx follow it
-// and are compared by their low parts.
+// come before the bucket of hx; inside the bucket they are ordered by their
+// low parts.
 __device__ __forceinline__ uint64_t ef_rank(const EFDev& e, uint64_t x) {
   if (e.m == 0) return 0;
   const uint64_t hx = x >> e.l;
   if (hx >= e.n_zeros) return e.m;
-  uint64_t i = 0, p = 0;
-  if (hx > 0) {
-    const uint64_t p0 = ef_zero_pos(e, hx - 1);
-    i = p0 - (hx - 1);
-    p = p0 + 1;
-  }
   const uint64_t xl = e.l ? (x & ((1ull << e.l) - 1)) : 0;
-  while (i < e.m && ((e.H[p >> 6] >> (p & 63)) & 1ull) && ef_low(e, i) < xl) {
-    ++i;
-    ++p;
-  }
-  return i;
+  uint64_t i, c = 0;
+  ef_bucket(e, hx, &i, xl == 0 ? nullptr : &c);  // a row start (low part 0) needs no run length
+  return xl == 0 ? i : ef_low_bound(e, i, c, xl);
 }
 
-// Is x a code of the list?  The scan of rank(x) stops at the first code with
-// high part hx and low part at least x's: x is present exactly when that
-// position holds a one whose low part equals x's.
-__device__ __forceinline__ bool ef_contains(const EFDev& e, uint64_t x) {
-  if (e.m == 0) return false;
-  const uint64_t hx = x >> e.l;
-  if (hx >= e.n_zeros) return false;
-  uint64_t i = 0, p = 0;
-  if (hx > 0) {
-    const uint64_t p0 = ef_zero_pos(e, hx - 1);
-    i = p0 - (hx - 1);
-    p = p0 + 1;
-  }
-  const uint64_t xl = e.l ? (x & ((1ull << e.l) - 1)) : 0;
-  while (i < e.m && ((e.H[p >> 6] >> (p & 63)) & 1ull)) {
-    const uint64_t lw = ef_low(e, i);
-    if (lw >= xl) return lw == xl;
-    ++i;
-    ++p;
-  }
-  return false;
-}
-
-// rank(x), and whether x is present (the scan's stopping code equals x).
+// rank(x), and whether x is present (the code at the rank equals x).
 __device__ __forceinline__ uint64_t ef_rank_has(const EFDev& e, uint64_t x, bool* has) {
   *has = false;
   if (e.m == 0) return 0;
   const uint64_t hx = x >> e.l;
   if (hx >= e.n_zeros) return e.m;
-  uint64_t i = 0, p = 0;
-  if (hx > 0) {
-    const uint64_t p0 = ef_zero_pos(e, hx - 1);
-    i = p0 - (hx - 1);
-    p = p0 + 1;
-  }
+  uint64_t i, c;
+  ef_bucket(e, hx, &i, &c);
   const uint64_t xl = e.l ? (x & ((1ull << e.l) - 1)) : 0;
-  while (i < e.m && ((e.H[p >> 6] >> (p & 63)) & 1ull)) {
-    const uint64_t lw = ef_low(e, i);
-    if (lw >= xl) {
-      *has = lw == xl;
-      return i;
-    }
-    ++i;
-    ++p;
-  }
-  return i;
+  const uint64_t j = ef_low_bound(e, i, c, xl);
+  *has = j < i + c && ef_low(e, j) == xl;
+  return j;
+}
+
+// Is x a code of the list?
+__device__ __forceinline__ bool ef_contains(const EFDev& e, uint64_t x) {
+  bool has;
+  (void)ef_rank_has(e, x, &has);
+  return has;
 }
 
 __device__ __forceinline__ int32_t ef_nbr(const EFDev& e, uint64_t idx) {
@@ -342,6 +349,7 @@ __global__ __launch_bounds__(256, 8) void k_walk_lane_ef(WalkArgs a, EFDev e, un
 // t are tested in the store itself.
 constexpr uint32_t kEfTile = 512;
 constexpr uint32_t kEfList = kEfTile;  // common-neighbour list of the probe route (in the idle tile)
+constexpr uint32_t kEfList2 = 256;     // common-neighbour list of the stream route (its own buffer)
 
 __device__ __forceinline__ bool lds_has(const int32_t* A, uint32_t n, int32_t x) {
   uint32_t lo = 0, hi = n;
@@ -353,9 +361,78 @@ __device__ __forceinline__ bool lds_has(const int32_t* A, uint32_t n, int32_t x)
   return lo < n && A[lo] == x;
 }
 
+// Cooperative decode of codes [i0, i0 + n) (n <= 64, wave-uniform) by the
+// whole wavefront, lane g getting code i0 + g: the ones of consecutive codes
+// are consecutive ones of H, so from the position `pos` of one number i0 the
+// lanes read 64 consecutive words of H at once, count their ones (a wave
+// scan), find the word holding their one by a bisection over the lanes'
+// counts (cross-lane reads) and its bit by a popcount bisection; the low
+// parts are consecutive fields of L.  Returns the lane's code; pos becomes
+// the position after the last decoded one (one select for a whole row).
+__device__ __forceinline__ uint64_t ef_decode_chunk(const EFDev& e, uint64_t i0, uint32_t n, uint64_t& pos, int gl) {
+  uint64_t code = 0, mine = 0;
+  uint32_t got = 0;
+  uint64_t w0 = pos >> 6;
+  uint64_t mask0 = ~0ull << (pos & 63);
+  while (got < n) {
+    const uint64_t wi = w0 + (uint64_t)gl;
+    const uint64_t word = (wi << 6) < e.h_bits ? e.H[wi] & (gl == 0 ? mask0 : ~0ull) : 0ull;
+    const uint32_t incl = wave_incl_scan_u32((uint32_t)__popcll(word));
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const uint32_t r = (uint32_t)gl - got;  // this lane's one within the round
+    const bool want = (uint32_t)gl >= got && (uint32_t)gl < n && r < total;
+    // first lane whose inclusive count exceeds r (every lane takes part in the reads)
+    int lo = 0, hi = 63;
+    for (int it = 0; it < 6; ++it) {
+      const int mid = (lo + hi) >> 1;
+      const uint32_t cm = (uint32_t)__shfl((int)incl, mid, 64);
+      if (cm > r) hi = mid;
+      else lo = mid + 1;
+    }
+    const int L = lo;
+    const uint32_t cL = (uint32_t)__shfl((int)incl, L, 64);
+    const uint32_t wlo = (uint32_t)__shfl((int)(uint32_t)word, L, 64);
+    const uint32_t whi = (uint32_t)__shfl((int)(uint32_t)(word >> 32), L, 64);
+    if (want) {
+      const uint64_t wL = (uint64_t)wlo | ((uint64_t)whi << 32);
+      const uint32_t excl = cL - (uint32_t)__popcll(wL);
+      const uint64_t p = ((w0 + (uint64_t)L) << 6) + nth_set_bit(wL, r - excl);
+      mine = p;
+      code = ((p - (i0 + (uint64_t)gl)) << e.l) | ef_low(e, i0 + (uint64_t)gl);
+    }
+    got += total < n - got ? total : n - got;
+    w0 += 64;
+    mask0 = ~0ull;
+  }
+  const uint64_t plast = (uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, (int)(n - 1)) |
+                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), (int)(n - 1)) << 32);
+  pos = plast + 1;
+  return code;
+}
+
+// First j in [lo, hi) with pred(j) (monotone), or hi: 64 evenly spaced
+// probes per round across the wavefront.
+template <typename P>
+__device__ __forceinline__ uint32_t wave_first(uint32_t lo, uint32_t hi, int gl, P pred) {
+  while (hi - lo > 64u) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t j = lo + (uint32_t)(gl + 1) * step - 1;
+    const bool pr = j < hi ? pred(j) : true;
+    const uint64_t m = grp_ballot<64>(pr, 0);
+    if (m == 0) return hi;
+    const int f = __ffsll((unsigned long long)m) - 1;
+    const uint32_t jf = (uint32_t)grp_bcast_i32<64>((int32_t)j, f);
+    lo = lo + (uint32_t)f * step;
+    if (jf < hi) hi = jf;
+  }
+  const uint32_t j = lo + (uint32_t)gl;
+  const uint64_t m = grp_ballot<64>(j < hi && pred(j), 0);
+  return m ? lo + (uint32_t)(__ffsll((unsigned long long)m) - 1) : hi;
+}
+
 template <bool WEIGHTED, typename RT>
 __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, uint64_t w, int gl, int32_t* bufA,
-                                             int32_t* bufB) {
+                                             int32_t* bufB, uint32_t* lbuf) {
   constexpr int G = 64;
   const RT* __restrict__ R = (const RT*)a.g.R;
   const uint64_t P16 = a.P16, Q16 = a.Q16;
@@ -391,22 +468,34 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
         if (S == 0) break;
         const uint64_t T = scale_draw(r, S);
         jsel = WEIGHTED ? upper_bound_gt(R + lo, d, T) : (uint32_t)T;
-        if (stage)
-          for (uint32_t j = (uint32_t)gl; j < d; j += G) nxt[j] = ef_nbr(e, lo + j);
+        if (stage) {
+          uint64_t hpos = ef_one_pos(e, lo);
+          for (uint32_t c = 0; c < d; c += G) {
+            const uint32_t nn = d - c < (uint32_t)G ? d - c : (uint32_t)G;
+            const uint64_t code = ef_decode_chunk(e, lo + c, nn, hpos, gl);
+            if (c + (uint32_t)gl < d) nxt[c + gl] = (int32_t)(code & ((1ull << e.k) - 1));
+          }
+        }
       } else {
         bool done = false;
+        // The positions in N(v) of the common neighbours (x in N(t), x != t),
+        // their weight sum and the position of t, by one of two routes; then
+        // the draw is located through them and a search of the row prefix
+        // between two of them, B_j = Q16 R_j + (C16 - Q16) sum_{common c <= j}
+        // w_c + (P16 - Q16) w_t [j >= pt] (mod 2^64, exact).  A list longer than
+        // its LDS buffer falls back to the two-pass stream below.
+        uint32_t* lpos = lbuf;
+        uint32_t lcap = kEfList2;
+        uint32_t cnt = 0, pt = 0;
+        bool has_t = false;
+        uint64_t cw = 0;
         if (d > kEfTile && ((uint64_t)td + 1) * 4 < d) {
-          // Probe route: rank every key of N(t) (and t) into N(v).  Hits are
-          // the common neighbours' positions, in increasing order; the draw
-          // is located through them and a bisection of the row prefix between
-          // two of them, B_j = Q16 R_j + (C16 - Q16) sum_{common c <= j} w_c
-          // + (P16 - Q16) w_t [j >= pt] (mod 2^64, exact).
-          // rows longer than the tile are not staged, so nxt holds the list
-          uint32_t* const lpos = reinterpret_cast<uint32_t*>(nxt);
+          // Probe route: rank every key of N(t) (and t) into N(v).  Hits come
+          // in increasing position.  Rows longer than the tile are not staged,
+          // so nxt holds the list.
+          lpos = reinterpret_cast<uint32_t*>(nxt);
+          lcap = kEfList;
           const uint64_t vc0 = (uint64_t)v << e.k;
-          uint32_t cnt = 0, pt = 0;
-          bool has_t = false;
-          uint64_t cw = 0;
           for (uint32_t c = 0; c < td + 1; c += G) {
             const uint32_t k = c + (uint32_t)gl;
             const bool tkey = k == td;
@@ -426,61 +515,88 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
             if (common) {
               cw += WEIGHTED ? weight_at(R, lo, pos) : 1ull;
               const uint32_t idx = cnt + (uint32_t)__popcll(m & lt_mask);
-              if (idx < kEfList) lpos[idx] = pos;
+              if (idx < lcap) lpos[idx] = pos;
             }
             cnt += (uint32_t)__popcll(m);
           }
-          if (cnt <= kEfList) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const uint64_t cdel = (uint64_t)kC16 - Q16, rdel = P16 - Q16;
-            const uint64_t CW = grp_sum<G>(cw);
-            const uint64_t wt = has_t ? (WEIGHTED ? weight_at(R, lo, pt) : 1ull) : 0ull;
-            const uint64_t retw = rdel * wt;
-            const uint64_t S = WEIGHTED ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
-            const uint64_t total = Q16 * S + cdel * CW + retw;
-            if (total == 0) break;
-            const uint64_t T = scale_draw(r, total);
-            // first listed position whose B exceeds T: the segment before it
-            // holds no common neighbour
-            uint64_t E = 0, Eseg = CW;
-            uint32_t seg_lo = 0, seg_end = d, lastpos = 0;
-            bool found = false, any = false;
-            for (uint32_t c = 0; c < cnt; c += G) {
-              const uint32_t k = c + (uint32_t)gl;
-              const bool act = k < cnt;
-              const uint32_t p = act ? lpos[k] : 0u;
-              const uint64_t wk = act ? (WEIGHTED ? weight_at(R, lo, p) : 1ull) : 0ull;
-              const uint64_t inc = grp_incl_scan<G>(wk, gl);
-              const uint64_t Ek = E + inc;
-              const uint64_t Bk = Q16 * Rv(p) + cdel * Ek + ((has_t && p >= pt) ? retw : 0ull);
-              const uint64_t mb = grp_ballot<G>(act && Bk > T, 0);
-              if (mb) {
-                const int f = __ffsll((unsigned long long)mb) - 1;
-                Eseg = grp_bcast<G>(Ek - wk, f);
-                seg_end = (uint32_t)grp_bcast_i32<G>((int32_t)p, f);
-                const uint32_t pprev = (uint32_t)grp_bcast_i32<G>((int32_t)p, f > 0 ? f - 1 : 0);
-                seg_lo = f > 0 ? pprev + 1 : (any ? lastpos + 1 : 0u);
-                found = true;
-                break;
-              }
-              const uint32_t nact = min((uint32_t)G, cnt - c);
-              lastpos = (uint32_t)grp_bcast_i32<G>((int32_t)p, (int)nact - 1);
-              any = true;
-              E += grp_bcast<G>(inc, G - 1);
+        } else {
+          // Stream route: N(v) decoded 64 codes at a time from one select
+          // (staged in LDS when short), each candidate tested against N(t)
+          // in LDS or in the store.
+          uint64_t hpos = ef_one_pos(e, lo);
+          const uint64_t tc0 = (uint64_t)t << e.k;
+          const uint64_t kmask = (1ull << e.k) - 1;
+          for (uint32_t c = 0; c < d; c += G) {
+            const uint32_t nn = d - c < (uint32_t)G ? d - c : (uint32_t)G;
+            const uint64_t code = ef_decode_chunk(e, lo + c, nn, hpos, gl);
+            const uint32_t j = c + (uint32_t)gl;
+            const bool act = j < d;
+            const int32_t x = (int32_t)(code & kmask);
+            if (act && stage) nxt[j] = x;
+            const bool isret = act && x == t;
+            const uint64_t mt = grp_ballot<G>(isret, 0);
+            if (mt) {
+              has_t = true;
+              pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
             }
-            if (!found) seg_lo = any ? lastpos + 1 : 0u;
-            // first j in [seg_lo, seg_end) with B_j > T (common weight Eseg
-            // there); none: the listed position seg_end itself
-            uint32_t jl = seg_lo, jh = seg_end;
-            while (jl < jh) {
-              const uint32_t mid = jl + ((jh - jl) >> 1);
-              if (Q16 * Rv(mid) + cdel * Eseg + ((has_t && mid >= pt) ? retw : 0ull) > T) jh = mid;
-              else jl = mid + 1;
+            const bool common =
+                act && !isret && (t_in_lds ? lds_has(cur, td, x) : ef_contains(e, tc0 | (uint64_t)(uint32_t)x));
+            const uint64_t m = grp_ballot<G>(common, 0);
+            if (common) {
+              cw += WEIGHTED ? weight_at(R, lo, j) : 1ull;
+              const uint32_t idx = cnt + (uint32_t)__popcll(m & lt_mask);
+              if (idx < lcap) lpos[idx] = j;
             }
-            jsel = jl;
-            done = true;
+            cnt += (uint32_t)__popcll(m);
           }
+        }
+        if (cnt <= lcap) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const uint64_t cdel = (uint64_t)kC16 - Q16, rdel = P16 - Q16;
+          const uint64_t CW = grp_sum<G>(cw);
+          const uint64_t wt = has_t ? (WEIGHTED ? weight_at(R, lo, pt) : 1ull) : 0ull;
+          const uint64_t retw = rdel * wt;
+          const uint64_t S = WEIGHTED ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
+          const uint64_t total = Q16 * S + cdel * CW + retw;
+          if (total == 0) break;
+          const uint64_t T = scale_draw(r, total);
+          // first listed position whose B exceeds T: the segment before it
+          // holds no common neighbour
+          uint64_t E = 0, Eseg = CW;
+          uint32_t seg_lo = 0, seg_end = d, lastpos = 0;
+          bool found = false, any = false;
+          for (uint32_t c = 0; c < cnt; c += G) {
+            const uint32_t k = c + (uint32_t)gl;
+            const bool act = k < cnt;
+            const uint32_t p = act ? lpos[k] : 0u;
+            const uint64_t wk = act ? (WEIGHTED ? weight_at(R, lo, p) : 1ull) : 0ull;
+            const uint64_t inc = grp_incl_scan<G>(wk, gl);
+            const uint64_t Ek = E + inc;
+            const uint64_t Bk = Q16 * Rv(p) + cdel * Ek + ((has_t && p >= pt) ? retw : 0ull);
+            const uint64_t mb = grp_ballot<G>(act && Bk > T, 0);
+            if (mb) {
+              const int f = __ffsll((unsigned long long)mb) - 1;
+              Eseg = grp_bcast<G>(Ek - wk, f);
+              seg_end = (uint32_t)grp_bcast_i32<G>((int32_t)p, f);
+              const uint32_t pprev = (uint32_t)grp_bcast_i32<G>((int32_t)p, f > 0 ? f - 1 : 0);
+              seg_lo = f > 0 ? pprev + 1 : (any ? lastpos + 1 : 0u);
+              found = true;
+              break;
+            }
+            const uint32_t nact = min((uint32_t)G, cnt - c);
+            lastpos = (uint32_t)grp_bcast_i32<G>((int32_t)p, (int)nact - 1);
+            any = true;
+            E += grp_bcast<G>(inc, G - 1);
+          }
+          if (!found) seg_lo = any ? lastpos + 1 : 0u;
+          // first j in [seg_lo, seg_end) with B_j > T (common weight Eseg
+          // there); none: the listed position seg_end itself
+          const uint64_t base = cdel * Eseg;
+          jsel = wave_first(seg_lo, seg_end, gl, [&](uint32_t j) {
+            return Q16 * Rv(j) + base + ((has_t && j >= pt) ? retw : 0ull) > T;
+          });
+          done = true;
         }
         if (!done) {
         const uint64_t tc0 = (uint64_t)t << e.k;
@@ -562,6 +678,7 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
 template <bool WEIGHTED, typename RT>
 __global__ __launch_bounds__(256, 8) void k_walk_n2v_ef(WalkArgs a, EFDev e, unsigned long long* ctr, uint32_t chunk) {
   __shared__ int32_t tiles[4][2][kEfTile];
+  __shared__ uint32_t lists[4][kEfList2];
   const int gl = threadIdx.x & 63;
   // the wave index is uniform: per-walker state goes to scalar registers
   const int wv = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
@@ -576,7 +693,7 @@ __global__ __launch_bounds__(256, 8) void k_walk_n2v_ef(WalkArgs a, EFDev e, uns
       end = min(w + chunk, a.nwalks);
     }
     if (w >= a.nwalks) break;
-    wave_walk_ef<WEIGHTED, RT>(a, e, w, gl, tiles[wv][0], tiles[wv][1]);
+    wave_walk_ef<WEIGHTED, RT>(a, e, w, gl, tiles[wv][0], tiles[wv][1], lists[wv]);
     w += ctr ? 1 : waves;
   }
 }

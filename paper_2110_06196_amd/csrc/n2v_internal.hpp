@@ -101,6 +101,7 @@ struct LaunchCfg {
   int grid_blocks = 0;        // 0 = derive from occupancy
   int full = 1;               // queue kernel with approximated steps and the two-pass route (0: exact routes only)
   int w32 = 0;                // queue kernel for weighted graphs with 32-bit prefixes only (every request's graph)
+  int lists = 0;              // every edge of every graph of the launch keeps a stored list
 };
 
 // Output slots a walker group of fewer than 16 lanes collects in LDS before

@@ -84,6 +84,13 @@ int all_w32(const std::vector<Prepared>& reqs) {
   return 1;
 }
 
+// Whether every node2vec request's graph keeps a stored list for every edge.
+int all_lists(const std::vector<Prepared>& reqs) {
+  for (const Prepared& r : reqs)
+    if (r.args.path == (uint32_t)Path::kGeneric && !r.full_lists) return 0;
+  return 1;
+}
+
 // Split every request into chunks of roughly `target` units and order them
 // longest-estimated-first.  A wavefront runs one chunk at a time: lane-path
 // chunks are whole multiples of 64 rows (one per lane) and node2vec chunks
@@ -257,6 +264,7 @@ int autotune(BatchPlan* p) {
     LaunchCfg c = shape_cfg(sh[0], sh[1], sh[2]);
     c.full = needs_full(p->reqs) ? 1 : 0;
     c.w32 = all_w32(p->reqs);
+    c.lists = all_lists(p->reqs);
     if (block_lds_bytes(c.lanes_per_walker, c.lds_tile, c.list_cap) > p->di.lds_per_block_max) continue;
     const std::vector<QueueChunk> sample =
         make_chunks(p->reqs, chunk_target(total * kFrac, c, p->di), group_unit(c), nullptr, kFrac);
@@ -632,6 +640,7 @@ int n2v_walks_batched(const n2v_request_desc_t* reqs, uint32_t n_reqs, void* hip
   apply_tuning_override(&cfg, di);
   cfg.full = needs_full(pr) ? 1 : 0;
   cfg.w32 = all_w32(pr);
+  cfg.lists = all_lists(pr);
   std::vector<QueueChunk> chunks = make_chunks(pr, chunk_target(total, cfg, di), group_unit(cfg), nullptr);
   if (chunks.empty()) return N2V_OK;
   if (chunks.size() > (1u << 30)) return fail(N2V_ERR_INVALID_ARG, "too many chunks");
@@ -673,6 +682,7 @@ int n2v_walks_batched_noalloc(const n2v_request_desc_t* reqs, uint32_t n_reqs, v
   apply_tuning_override(&cfg, di);
   cfg.full = needs_full(pr) ? 1 : 0;
   cfg.w32 = all_w32(pr);
+  cfg.lists = all_lists(pr);
   // table layout as in upload_tables: requests | chunks | head counter
   const size_t rb = pr.size() * sizeof(WalkArgs);
   const size_t off_c = (rb + 255) / 256 * 256;
@@ -727,6 +737,7 @@ int n2v_batch_create(const n2v_request_desc_t* reqs, uint32_t n_reqs, uint32_t f
   p->cfg = batch_default_cfg(p->reqs, p->di);
   p->cfg.full = needs_full(p->reqs) ? 1 : 0;
   p->cfg.w32 = all_w32(p->reqs);
+  p->cfg.lists = all_lists(p->reqs);
   if (flags & N2V_BATCH_AUTOTUNE) rc = autotune(p);
   apply_tuning_override(&p->cfg, p->di);  // an explicit n2v_set_tuning wins
   // the final chunking follows the chosen shape

@@ -399,7 +399,10 @@ struct CtxArgs {
   uint32_t window = 0, stride = 0, h = 0, rp = 0;
 };
 
-template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS = false, bool CTX = false>
+// LISTS: every edge of the graph keeps a stored list and the route is
+// automatic, so a second-order step always searches a stored list and the
+// list-building routes are left out (fewer live registers: no spills).
+template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS = false, bool CTX = false, bool LISTS = false>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
                                            int mode_knob, const CtxArgs& cx = CtxArgs{}) {
   const int lane = threadIdx.x & 63;
@@ -702,7 +705,7 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
               }
             }
           }
-          if (!cached) {
+          if (!LISTS && !cached) {
             int mode = mode_knob;
             if (mode == kModeAuto || mode == kModeHubSets) {
               // dependent-latency estimate: global load = 100, LDS load = 15
@@ -1096,10 +1099,11 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
 }
 
 // Occupancy bounds (measured): one walker per wavefront runs 8 waves per SIMD
-// with scalar spills; 4- and 8-lane groups, which serve graphs whose edges all
-// keep a stored list, run 5 and 6 waves with a few vector spills.
-template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS>
-__global__ __launch_bounds__(256, G == 64 ? 8 : (G == 4 ? 5 : (G == 8 ? 6 : 1))) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
+// with scalar spills; 4- and 8-lane groups run 5 and 6 waves with a few vector
+// spills; the lists-only 4-lane variant runs 7 (72 registers, a 20-byte spill:
+// faster than 6 waves without spill and than 8 with more).
+template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS, bool LISTS = false>
+__global__ __launch_bounds__(256, G == 64 ? 8 : (G == 4 ? (LISTS ? 7 : 5) : (G == 8 ? 6 : 1))) void k_walk_n2v(WalkArgs a, int tile, int cap, int mode_knob,
                                                                                    unsigned long long* ctr, uint32_t chunk) {
   extern __shared__ int32_t lds[];
   // with one walker per wavefront the group index is uniform: say so, so that
@@ -1122,7 +1126,7 @@ __global__ __launch_bounds__(256, G == 64 ? 8 : (G == 4 ? 5 : (G == 8 ? 6 : 1)))
       }
     }
     if (w >= a.nwalks) break;
-    group_walk<G, WEIGHTED, RT, FULL, HEADS>(a, w, mem, tile, cap, mode_knob);
+    group_walk<G, WEIGHTED, RT, FULL, HEADS, false, LISTS>(a, w, mem, tile, cap, mode_knob);
     w += ctr ? 1 : ngroups;
   }
 }
@@ -1273,8 +1277,8 @@ __device__ __forceinline__ WalkArgs from_global(const WalkArgsG& r) {
 // (64 / G)-th walk of it.
 // W32: every request's graph is weighted with 32-bit prefixes, so only those
 // walk variants are compiled in (fewer live registers, fewer spills).
-template <int G, bool FULL, bool W32>
-__global__ __launch_bounds__(256, G == 64 ? 7 : (G == 4 ? 5 : 1)) void k_walk_queue(const WalkArgs* __restrict__ reqs,
+template <int G, bool FULL, bool W32, bool LISTS = false>
+__global__ __launch_bounds__(256, G == 64 ? 7 : (G == 4 ? (LISTS ? 7 : 5) : 1)) void k_walk_queue(const WalkArgs* __restrict__ reqs,
                                                     const QueueChunk* __restrict__ chunks, uint32_t nchunks,
                                                     uint32_t* __restrict__ head, int tile, int cap,
                                                     int mode_knob) {
@@ -1301,7 +1305,8 @@ __global__ __launch_bounds__(256, G == 64 ? 7 : (G == 4 ? 5 : 1)) void k_walk_qu
         }
       }
     } else if (W32) {
-      for (uint64_t w = ch.w0 + giw; w < ch.w1; w += GPW) group_walk<G, true, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
+      for (uint64_t w = ch.w0 + giw; w < ch.w1; w += GPW)
+        group_walk<G, true, uint32_t, FULL, false, false, LISTS>(a, w, mem, tile, cap, mode_knob);
     } else if (a.g.W == nullptr) {
       for (uint64_t w = ch.w0 + giw; w < ch.w1; w += GPW) group_walk<G, false, uint32_t, FULL>(a, w, mem, tile, cap, mode_knob);
     } else if (a.g.r_bytes == 8) {
@@ -1398,13 +1403,20 @@ hipError_t go_n2v(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, hi
   // 64-lane groups on graphs with destination heads or hub sets take the
   // variant that searches heads and looks keys up in the sets
   const bool heads = G == 64 && (a.g.HD != nullptr || a.g.hub_sets != nullptr);
+  // 4-lane groups on graphs whose edges all keep a stored list (automatic
+  // route) take the variant without the list-building routes
+  const bool lists = G == 4 && WEIGHTED && sizeof(RT) == 4 && cfg.lists && !full && cfg.mode == kModeAuto;
   auto k = full ? (heads ? k_walk_n2v<G, WEIGHTED, RT, true, G == 64> : k_walk_n2v<G, WEIGHTED, RT, true, false>)
-                : (heads ? k_walk_n2v<G, WEIGHTED, RT, false, G == 64> : k_walk_n2v<G, WEIGHTED, RT, false, false>);
+                : (heads ? k_walk_n2v<G, WEIGHTED, RT, false, G == 64>
+                         : (lists ? k_walk_n2v<G, WEIGHTED, RT, false, false, G == 4 && WEIGHTED && sizeof(RT) == 4>
+                                  : k_walk_n2v<G, WEIGHTED, RT, false, false>));
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
+  // the lists-only variant stages no row and builds no list in LDS
+  const int tile = lists ? 0 : cfg.lds_tile, cap = lists ? 0 : cfg.list_cap;
+  const size_t lds = (size_t)gpb * group_lds_words(tile, cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
   return with_walk_counter(di, st, [&](unsigned long long* ctr) {
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cfg.mode, ctr,
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, tile, cap, cfg.mode, ctr,
                        walk_chunk(a.nwalks, (uint64_t)blocks * gpb));
     return hipGetLastError();
   });
@@ -1425,9 +1437,17 @@ hipError_t go_n2v_g(const WalkArgs& a, const LaunchCfg& cfg, const DevInfo& di, 
 // route only when a request of the launch needs them.
 inline bool queue_full(const LaunchCfg& cfg) { return cfg.full != 0 || cfg.mode == kModeTwoPass; }
 
+// 4-lane groups whose requests' graphs are all weighted (32-bit prefixes)
+// and keep a stored list for every edge: the lists-only queue kernel, which
+// stages no row and builds no list in LDS.
+inline bool queue_lists(const LaunchCfg& cfg) {
+  return cfg.lanes_per_walker == 4 && cfg.w32 && cfg.lists && !queue_full(cfg) && cfg.mode == kModeAuto;
+}
+
 template <int G>
 auto queue_kernel(const LaunchCfg& cfg) {
   const bool full = queue_full(cfg);
+  if (G == 4 && queue_lists(cfg)) return k_walk_queue<G, false, true, true>;
   if (cfg.w32) return full ? k_walk_queue<G, true, true> : k_walk_queue<G, false, true>;
   return full ? k_walk_queue<G, true, false> : k_walk_queue<G, false, false>;
 }
@@ -1437,11 +1457,12 @@ hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nch
                     const LaunchCfg& cfg, const DevInfo& di, hipStream_t st) {
   auto k = queue_kernel<G>(cfg);
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
+  const bool lists = queue_lists(cfg);
+  const int tile = lists ? 0 : cfg.lds_tile, cap = lists ? 0 : cfg.list_cap;
+  const size_t lds = (size_t)gpb * group_lds_words(tile, cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, ((uint64_t)nchunks + gpb - 1) / gpb, di);
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, head);
-  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, reqs, chunks, nchunks, head, cfg.lds_tile,
-                     cfg.list_cap, cfg.mode);
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, reqs, chunks, nchunks, head, tile, cap, cfg.mode);
   return hipGetLastError();
 }
 
@@ -1450,7 +1471,8 @@ hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nch
 int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks) {
   const int G = cfg.lanes_per_walker == 4 ? 4 : (cfg.lanes_per_walker == 16 ? 16 : (cfg.lanes_per_walker == 32 ? 32 : 64));
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * group_lds_words(cfg.lds_tile, cfg.list_cap, G) * sizeof(int32_t);
+  const bool lists = queue_lists(cfg);
+  const size_t lds = (size_t)gpb * group_lds_words(lists ? 0 : cfg.lds_tile, lists ? 0 : cfg.list_cap, G) * sizeof(int32_t);
   const uint64_t work = ((uint64_t)nchunks + gpb - 1) / gpb;
   if (G == 4) return grid_for(queue_kernel<4>(cfg), lds, work, di);
   if (G == 16) return grid_for(queue_kernel<16>(cfg), lds, work, di);
