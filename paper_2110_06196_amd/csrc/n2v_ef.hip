@@ -159,6 +159,48 @@ __device__ __forceinline__ bool ef_contains(const EFDev& e, uint64_t x) {
   return has;
 }
 
+// The row of node v: lo = rank(phi(v, 0)) and d = rank(phi(v + 1, 0)) - lo.
+// When phi(v, 0) has no low bits (l <= k) both ranks are zero positions, the
+// second hx1 - hx0 zeros after the first: one select and a continued word
+// scan instead of two selects.
+__device__ __forceinline__ void ef_row(const EFDev& e, int32_t v, uint64_t* lo, uint32_t* d) {
+  const uint64_t x0 = (uint64_t)(uint32_t)v << e.k, x1 = ((uint64_t)(uint32_t)v + 1) << e.k;
+  if (e.l > e.k || e.m == 0) {
+    *lo = ef_rank(e, x0);
+    *d = (uint32_t)(ef_rank(e, x1) - *lo);
+    return;
+  }
+  const uint64_t hx0 = x0 >> e.l, hx1 = x1 >> e.l;
+  if (hx0 >= e.n_zeros) {
+    *lo = e.m;
+    *d = 0;
+    return;
+  }
+  uint64_t i0 = 0, q = 0;  // zero number hx0 - 1 ends the codes below x0; the scan goes on from q
+  if (hx0 > 0) {
+    const uint64_t p0 = ef_zero_pos(e, hx0 - 1);
+    i0 = p0 - (hx0 - 1);
+    q = p0 + 1;
+  }
+  *lo = i0;
+  if (hx1 >= e.n_zeros) {
+    *d = (uint32_t)(e.m - i0);
+    return;
+  }
+  // zero number hx1 - 1: the (hx1 - 1 - (hx0 ? hx0 : 0))-th zero from q (0-based)
+  uint64_t r = (hx1 - 1) - (hx0 > 0 ? hx0 : 0);
+  uint64_t w = q >> 6;
+  uint64_t b = ~e.H[w] & (~0ull << (q & 63));
+  while (true) {
+    const uint32_t c = (uint32_t)__popcll(b);
+    if (r < c) break;
+    r -= c;
+    b = ~e.H[++w];
+  }
+  const uint64_t p1 = (w << 6) + nth_set_bit(b, (uint32_t)r);
+  *d = (uint32_t)(p1 - (hx1 - 1) - i0);
+}
+
 __device__ __forceinline__ int32_t ef_nbr(const EFDev& e, uint64_t idx) {
   return (int32_t)(ef_select(e, idx) & ((1ull << e.k) - 1));
 }
@@ -274,9 +316,11 @@ __device__ __forceinline__ void lane_walk_ef(const WalkArgs& a, const EFDev& e, 
     row[0] = start;
     len = 1;
     int32_t v = start, t = -1;
-    uint64_t lo = ef_rank(e, (uint64_t)v << e.k);
+    uint64_t lo;
+    uint32_t dnext;
+    ef_row(e, v, &lo, &dnext);
     for (uint32_t s = 1; s < a.L; ++s) {
-      const uint32_t d = (uint32_t)(ef_rank(e, ((uint64_t)v + 1) << e.k) - lo);
+      const uint32_t d = dnext;
       if (d == 0) break;  // dead end
       const uint64_t r = philox_draw(a.seed, s, wid);
       uint32_t j;
@@ -313,7 +357,7 @@ __device__ __forceinline__ void lane_walk_ef(const WalkArgs& a, const EFDev& e, 
       len = s + 1;
       t = v;
       v = x;
-      lo = ef_rank(e, (uint64_t)v << e.k);
+      ef_row(e, v, &lo, &dnext);
     }
   }
   for (uint32_t s = len; s < a.L; ++s) row[s] = -1;
@@ -449,19 +493,21 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
     bool t_in_lds = false;
     uint32_t td = 0;
     uint64_t tlo = 0;
-    uint64_t lo = ef_rank(e, (uint64_t)v << e.k);
+    uint64_t lo;
+    uint32_t dnext;
+    ef_row(e, v, &lo, &dnext);
     const uint64_t lt_mask = gl == 0 ? 0ull : (~0ull >> (64 - gl));
     auto Rv = [&](uint32_t j) -> uint64_t { return WEIGHTED ? (uint64_t)R[lo + j] : (uint64_t)j + 1ull; };
     // lane gl holds the draw of step s1 + gl: one vector Philox evaluation
     // every 64 steps instead of a scalar one per step
     uint64_t rdraw = 0;
     for (uint32_t s = 1; s < a.L; ++s) {
-      const uint32_t d = (uint32_t)(ef_rank(e, ((uint64_t)v + 1) << e.k) - lo);
+      const uint32_t d = dnext;
       if (d == 0) break;
       const uint32_t sk = (s - 1u) & 63u;
       if (sk == 0) rdraw = philox_draw(a.seed, s + (uint32_t)gl, wid);
       const uint64_t r = wave_read_u64(rdraw, (int)sk);
-      const bool stage = a.second_order && d <= kEfTile;
+      bool stage = a.second_order && d <= kEfTile;
       uint32_t jsel = d;
       if (!a.second_order || t < 0) {
         const uint64_t S = WEIGHTED ? (uint64_t)R[lo + d - 1] : (uint64_t)d;
@@ -489,12 +535,22 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
         uint32_t cnt = 0, pt = 0;
         bool has_t = false;
         uint64_t cw = 0;
-        if (d > kEfTile && ((uint64_t)td + 1) * 4 < d) {
+        // route by a dependent-load estimate per 64 keys: a decoded candidate
+        // tested in LDS ~3, in the store ~17 (rank: a zero select, the bucket's
+        // run, a bisection of its low parts); a key of N(t) ranked into N(v)
+        // ~16 from LDS, ~19 decoded from the store
+        const uint64_t c_stream = (uint64_t)((d + G - 1) / G) * (t_in_lds ? 3u : 17u);
+        const uint64_t c_probe = (uint64_t)((td + 1 + G - 1) / G) * (t_in_lds ? 16u : 19u);
+        if (c_probe < c_stream) {
           // Probe route: rank every key of N(t) (and t) into N(v).  Hits come
-          // in increasing position.  Rows longer than the tile are not staged,
-          // so nxt holds the list.
-          lpos = reinterpret_cast<uint32_t*>(nxt);
-          lcap = kEfList;
+          // in increasing position.  The list goes to the tile of N(v) when the
+          // row is too long to stage, else to the list buffer (and the row is
+          // not staged for the next step).
+          if (d > kEfTile) {
+            lpos = reinterpret_cast<uint32_t*>(nxt);
+            lcap = kEfList;
+          }
+          stage = false;
           const uint64_t vc0 = (uint64_t)v << e.k;
           for (uint32_t c = 0; c < td + 1; c += G) {
             const uint32_t k = c + (uint32_t)gl;
@@ -663,7 +719,7 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
         nxt = tmp;
       }
       v = x;
-      lo = ef_rank(e, (uint64_t)v << e.k);
+      ef_row(e, v, &lo, &dnext);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
