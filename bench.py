@@ -75,7 +75,7 @@ def parse():
                                                                       "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="write the corpus kernels' rocprofv3 summaries under profiles/")
     ap.add_argument("--summarize-kernel-profiles", nargs=2, metavar=("SET", "DIR"),
-                    help="SET = batched or big: write that kernel's profiles/*.txt from DIR/{trace,fetch,write,sq,"
+                    help="SET = batched, c2 or big: write that kernel's profiles/*.txt from DIR/{trace,fetch,write,sq,"
                          "tcc,cal_fetch,cal_write,cal_tcc} (rocprofv3 output of the commands they name) and exit")
     ap.add_argument("--summarize-profiles", nargs=7, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR",
                                                               "CAL_FETCH_DIR", "CAL_WRITE_DIR", "SQ_DIR",
@@ -139,14 +139,7 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "pmc_counters_chung_lu_1m.txt")
 def l2_hit_from_profiles(kernel: str, path: str = COUNTERS_FILE, files=WALK_SOURCES):
     """L2 hit rate of `kernel` from the committed rocprofv3 counter summary, if
     it was taken on the current kernel sources (else None)."""
-    if not os.path.exists(path):
-        return None
-    txt = open(path).read()
-    m = re.search(r"source_hash:\s*(\w+)", txt)
-    if not m or m.group(1) != kernel_source_hash(files):
-        return None
-    m = re.search(rf"^{re.escape(kernel)}\s+valu_insts_per_wave:.*l2_hit_rate:\s*([0-9.]+)", txt, re.M)
-    return float(m.group(1)) if m else None
+    return _profile_value(path, f"{kernel} l2_hit_rate", files)
 
 
 def _csvs(d, suffix):
@@ -977,6 +970,10 @@ PROFILE_SETS = {
     "batched": ("k_walk_queue", 3, 2, "python3 /root/repo/bench.py --config profile_batched --warmup 0 --steps {k}",
                 "64-graph / 4096-request batched node2vec workload (the headline's batched plan)",
                 (BATCHED_TRACE_FILE, BATCHED_TRAFFIC_FILE, BATCHED_COUNTERS_FILE, SECTOR_FILE)),
+    "c2": ("k_walk_n2v", 3, 2, "python3 /root/repo/bench.py --config chung_lu_1m --runs 0.25,4 --warmup 0 --steps {k} "
+                               "--cpu-seconds 0",
+           "1M-node Chung-Lu graph, node2vec (p, q) = (0.25, 4), 10 walks of 100 slots per node",
+           (TRACE_FILE, TRAFFIC_FILE, COUNTERS_FILE, os.path.join(ROOT, "profiles", "pmc_sectors_chung_lu_1m.txt"))),
     "big": ("k_walk_n2v", 1, 1, "python3 /root/repo/bench.py --config big --big-runs n2v --warmup 0 --steps {k} "
                                 "--cpu-seconds 0",
             "20M-node Chung-Lu graph, node2vec (p, q) = (1, 2), one walk of 80 slots per node",
