@@ -66,8 +66,9 @@ def test_traffic_needs_matching_source_hash(tmp_path):
 
 def test_l2_hit_needs_matching_source_hash(tmp_path):
     f = tmp_path / "c.txt"
+    # the counter summary's layout: derived figures, then the hit rate on a line of its own
     line = "k_walk_n2v valu_insts_per_wave: 1.0 vmem_rd_insts_per_wave: 1.0 lds_insts_per_wave: 0.0 " \
-           "wait_any_share_of_wave_cycles: 0.5 l2_hit_rate: 0.375\n"
+           "wait_any_share_of_wave_cycles: 0.5\nk_walk_n2v l2_hit_rate: 0.375\n"
     f.write_text("source_hash: 0000000000000000\n" + line)
     assert bench.l2_hit_from_profiles("k_walk_n2v", str(f)) is None
     f.write_text(f"source_hash: {bench.kernel_source_hash()}\n" + line)
