@@ -974,6 +974,12 @@ PROFILE_SETS = {
                                "--cpu-seconds 0",
            "1M-node Chung-Lu graph, node2vec (p, q) = (0.25, 4), 10 walks of 100 slots per node",
            (TRACE_FILE, TRAFFIC_FILE, COUNTERS_FILE, os.path.join(ROOT, "profiles", "pmc_sectors_chung_lu_1m.txt"))),
+    "c2fo": ("k_walk_lane", 3, 2, "python3 /root/repo/bench.py --config chung_lu_1m --runs 1,1 --warmup 0 --steps {k} "
+                                  "--cpu-seconds 0",
+             "1M-node Chung-Lu graph, first-order walks ((p, q) = (1, 1)), 10 walks of 100 slots per node",
+             tuple(os.path.join(ROOT, "profiles", f) for f in (
+                 "kernel_trace_chung_lu_1m_first_order.txt", "pmc_traffic_chung_lu_1m_first_order.txt",
+                 "pmc_counters_chung_lu_1m_first_order.txt", "pmc_sectors_chung_lu_1m_first_order.txt"))),
     "big": ("k_walk_n2v", 1, 1, "python3 /root/repo/bench.py --config big --big-runs n2v --warmup 0 --steps {k} "
                                 "--cpu-seconds 0",
             "20M-node Chung-Lu graph, node2vec (p, q) = (1, 2), one walk of 80 slots per node",

@@ -104,8 +104,8 @@ struct LaunchCfg {
   int lists = 0;              // every edge of every graph of the launch keeps a stored list
 };
 
-// Output slots a walker group of fewer than 16 lanes collects in LDS before
-// storing them (64 bytes).
+// Output slots per 64-byte line: what a walker group of fewer than 16 lanes
+// collects in LDS before storing it, and what a one-lane walker stages.
 constexpr uint32_t kOutStage = 16;
 
 // LDS words per walker group of g lanes: two staging tiles of the previous
@@ -115,9 +115,18 @@ __host__ __device__ constexpr int group_lds_words(int tile, int cap, int g) {
   return 2 * tile + 2 * cap + 2 * g + (g < 16 ? (int)kOutStage : 0);
 }
 
-// LDS bytes of a 256-thread block for a launch shape.
+// LDS words per wavefront of the batched kernel, which runs walker groups and
+// one-lane walkers in turn: the groups' regions or the one-lane walkers'
+// output stages (one line per lane), whichever is larger.
+__host__ __device__ constexpr int queue_wave_words(int tile, int cap, int g) {
+  return (64 / g) * group_lds_words(tile, cap, g) > 64 * (int)kOutStage ? (64 / g) * group_lds_words(tile, cap, g)
+                                                                         : 64 * (int)kOutStage;
+}
+
+// LDS bytes of a 256-thread block for a launch shape (the batched kernel's,
+// which is never less than the plain node2vec kernel's).
 inline size_t block_lds_bytes(int lanes_per_walker, int tile, int cap) {
-  return (size_t)(256 / lanes_per_walker) * (size_t)group_lds_words(tile, cap, lanes_per_walker) * 4;
+  return 4 * (size_t)queue_wave_words(tile, cap, lanes_per_walker) * 4;
 }
 
 // Device facts used to size grids.

@@ -56,9 +56,16 @@ namespace {
 
 enum { kFoUnw = 0, kFoW = 1, kRetUnw = 2, kRetW = 3 };
 
-// One whole walk (row w of request a) by one lane.
+// Output rows leave in whole 64-byte lines: a slot is staged until the slot
+// that ends its line (by address) is drawn, then the line is stored at once; a
+// line written piecemeal costs one write per piece once the random reads of
+// the walk have pushed it out of the cache.  Only the row's first and last
+// lines can be partial.
+
+// One whole walk (row w of request a) by one lane.  `st` is the lane's output
+// stage in LDS: slot k of the current line at st[64 * k].
 template <int MODE, typename RT>
-__device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
+__device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w, int32_t* st) {
   const uint64_t* __restrict__ O = a.g.O;
   const int32_t* __restrict__ D = a.g.D;
   const RT* __restrict__ R = (const RT*)a.g.R;
@@ -67,8 +74,25 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
     const int32_t start = a.starts[w % a.ns];
     const uint64_t wid = a.wid_base + w;
     uint32_t len = 0;
+    // slot of row position 0 within its line; every line before the one
+    // holding position s has been stored once s is staged
+    const uint32_t roff = (uint32_t)(((uintptr_t)row >> 2) & (kOutStage - 1));
+    auto put = [&](uint32_t s, int32_t x) {
+      const uint32_t k = (roff + s) & (kOutStage - 1);
+      st[64 * k] = x;
+      if (k == kOutStage - 1) {
+        if (s >= kOutStage - 1) {
+          int4* __restrict__ dst = (int4*)(row + (s - (kOutStage - 1)));
+#pragma unroll
+          for (uint32_t q = 0; q < kOutStage / 4; ++q)
+            dst[q] = make_int4(st[64 * (4 * q)], st[64 * (4 * q + 1)], st[64 * (4 * q + 2)], st[64 * (4 * q + 3)]);
+        } else {
+          for (uint32_t p = 0; p <= s; ++p) row[p] = st[64 * ((roff + p) & (kOutStage - 1))];
+        }
+      }
+    };
     if (start >= 0 && (int64_t)start < a.g.n) {
-      row[0] = start;
+      put(0, start);
       len = 1;
       int32_t v = start, t = -1;
       for (uint32_t s = 1; s < a.L; ++s) {
@@ -117,13 +141,16 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
           j = jl;
         }
         const int32_t x = D[lo + j];
-        row[s] = x;
+        put(s, x);
         len = s + 1;
         t = v;
         v = x;
       }
     }
-    for (uint32_t s = len; s < a.L; ++s) row[s] = -1;
+    // staged slots [s0, len) (the start of len's line, or 0), then the padding
+    const uint32_t lk = (roff + len) & (kOutStage - 1);
+    const uint32_t s0 = len > lk ? len - lk : 0u;
+    for (uint32_t p = s0; p < a.L; ++p) row[p] = p < len ? st[64 * ((roff + p) & (kOutStage - 1))] : -1;
     if (a.lens) a.lens[w] = (int32_t)len;
     if (a.steps && len > 1) atomicAdd(a.steps, (unsigned long long)(len - 1));
   }
@@ -131,6 +158,8 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w) {
 
 template <int MODE, typename RT>
 __global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a, unsigned long long* ctr, uint32_t chunk) {
+  __shared__ int32_t stage[256 * kOutStage];
+  int32_t* const st = stage + (threadIdx.x / 64u) * (64u * kOutStage) + (threadIdx.x & 63u);
   if (ctr) {
     // a wave takes 64 * chunk walks at a time from the launch counter
     const int lane = threadIdx.x & 63;
@@ -141,13 +170,13 @@ __global__ __launch_bounds__(256) void k_walk_lane(WalkArgs a, unsigned long lon
       const uint64_t base = wave_read_u64((uint64_t)c, 0);
       if (base >= a.nwalks) break;
       const uint64_t end = min(base + span, a.nwalks);
-      for (uint64_t w = base + lane; w < end; w += 64) lane_walk<MODE, RT>(a, w);
+      for (uint64_t w = base + lane; w < end; w += 64) lane_walk<MODE, RT>(a, w, st);
     }
     return;
   }
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nwalks; w += stride)
-    lane_walk<MODE, RT>(a, w);
+    lane_walk<MODE, RT>(a, w, st);
 }
 
 __device__ __forceinline__ bool lds_contains(const int32_t* A, uint32_t n, int32_t x) {
@@ -413,11 +442,10 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
   uint32_t* const lpos = (uint32_t*)(bufB + tile);
   uint32_t* const lw = lpos + cap;
   int32_t* const win = (int32_t*)(lw + cap);
-  // Output pieces of at least 64 bytes (a line left partly written costs a
-  // whole line of write traffic when it leaves the cache): groups of 16 or
-  // more lanes hold one slot per lane and store G slots at once; narrower
-  // groups collect kOutStage slots in LDS (after the merge window) and store
-  // them together.
+  // Output in whole lines (by address): groups of 16 or more lanes hold one
+  // slot per lane and store G slots (one to four lines) at once; narrower
+  // groups collect a line of kOutStage slots in LDS (after the merge window)
+  // and store it together.
   constexpr uint32_t OW = G >= 16 ? (uint32_t)G : kOutStage;
   int32_t* const ostage = win + 2 * G;
   int32_t* const ring = mem + group_lds_words(tile, cap, G);  // CTX only
@@ -447,16 +475,42 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
     const int32_t start = a.starts[w % a.ns];
     const uint64_t wid = a.wid_base + w;
     uint32_t len = 0;
-    int32_t ob = -1;  // output window: this lane holds slot s0 + gl
-    uint32_t s0 = 0;
+    // Row position s sits in slot (roff + s) mod OW of an OW-slot piece that
+    // starts on a line boundary; ob (G >= 16) is this lane's slot of the
+    // current piece.  Every piece before the one holding position s has been
+    // stored once s is staged.
+    const uint32_t roff = (uint32_t)(((uintptr_t)row >> 2) & (OW - 1));
+    int32_t ob = -1;
+    int32_t nf = (int32_t)(OW - 1 - roff);  // the next position that ends a piece
+    auto put = [&](uint32_t s, int32_t x) {
+      const uint32_t k = (uint32_t)((int32_t)s - nf - 1) & (OW - 1);
+      if constexpr (G >= 16) {
+        if ((uint32_t)gl == k) ob = x;
+      } else {
+        if (gl == 0) ostage[k] = x;
+      }
+      if ((int32_t)s != nf) return;
+      const int32_t ps = nf - (int32_t)(OW - 1);  // the piece's first position
+      nf += OW;
+      if constexpr (G >= 16) {
+        if (ps + gl >= 0) row[ps + gl] = ob;
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // OW / G back-to-back stores cover the line (only the row's first
+        // line can start before the row)
+#pragma unroll
+        for (int32_t kk = 0; kk < (int32_t)OW; kk += G)
+          if (ps + kk + gl >= 0) row[ps + kk + gl] = ostage[kk + gl];
+      }
+    };
     if (start >= 0 && (int64_t)start < a.g.n) {
       if constexpr (CTX) {
         if (gl == 0) ring[0] = start;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      } else if (gl == 0) {
-        if constexpr (G >= 16) ob = start;
-        else ostage[0] = start;
+      } else {
+        put(0, start);
       }
       len = 1;
       int32_t v = start, t = -1;
@@ -1033,22 +1087,8 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           if (s >= cx.h) emit(s - cx.h, (int64_t)s);
-        } else if constexpr (G >= 16) {
-          if ((uint32_t)gl == s % G) ob = xsel;
-          if (s % G == G - 1) {
-            row[s0 + gl] = ob;
-            s0 += G;
-            ob = -1;
-          }
         } else {
-          if (gl == 0) ostage[s % OW] = xsel;
-          if (s % OW == OW - 1) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (uint32_t k = 0; k < OW; k += G) row[s0 + k + gl] = ostage[k + gl];
-            s0 += OW;
-          }
+          put(s, xsel);
         }
         len = s + 1;
         t = v;
@@ -1079,18 +1119,32 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
       int32_t* __restrict__ pad = cx.C + (w * a.L + len) * (uint64_t)W2;
       const uint64_t words = (uint64_t)(a.L - len) * W2;
       for (uint64_t u = (uint64_t)gl; u < words; u += G) pad[u] = -1;
-    } else if constexpr (G >= 16) {
-      for (uint32_t s = s0; s < a.L; s += G) {
-        const uint32_t idx = s + gl;
-        if (idx < a.L) row[idx] = (s == s0 && idx < len) ? ob : -1;
-      }
     } else {
-      // slots [s0, len) are staged (len - s0 < OW), the rest are padding
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (uint32_t s = s0; s < a.L; s += G) {
-        const uint32_t idx = s + gl;
-        if (idx < a.L) row[idx] = idx < len ? ostage[idx - s0] : -1;
+      // positions [s0, len) (from the start of len's piece, or 0) are staged,
+      // the rest are padding
+      if constexpr (G < 16) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t s0 = nf >= (int32_t)(OW - 1) ? (uint32_t)(nf - (int32_t)(OW - 1)) : 0u;
+        for (uint32_t p = s0 + (uint32_t)gl; p < a.L; p += G)
+          row[p] = p < len ? ostage[(uint32_t)((int32_t)p - nf - 1) & (OW - 1)] : -1;
+      } else {
+      const uint32_t lk = (roff + len) & (OW - 1);
+      const uint32_t s0 = len > lk ? len - lk : 0u;
+      const int64_t first = (int64_t)s0 - (int64_t)((roff + s0) & (OW - 1));
+      for (int64_t base = first; base < (int64_t)a.L; base += OW) {
+        for (uint32_t kk = (uint32_t)gl; kk < OW; kk += G) {
+          const int64_t p = base + kk;
+          if (p >= (int64_t)s0 && p < (int64_t)a.L) {
+            int32_t val = -1;
+            if (p < (int64_t)len) {
+              if constexpr (G >= 16) val = ob;
+              else val = ostage[kk];
+            }
+            row[p] = val;
+          }
+        }
+      }
       }
     }
     if (a.lens && gl == 0) a.lens[w] = (int32_t)len;
@@ -1165,17 +1219,17 @@ __global__ __launch_bounds__(256) void k_walk_ctx(WalkArgs a, int tile, int cap,
 // with the same per-walk routines as the plain kernels.
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ __forceinline__ void lane_dispatch(const WalkArgs& a, uint64_t w) {
+__device__ __forceinline__ void lane_dispatch(const WalkArgs& a, uint64_t w, int32_t* st) {
   const bool weighted = a.g.W != nullptr;
   const bool r64 = a.g.r_bytes == 8;
   if (a.path == (uint32_t)Path::kFirstOrder) {
-    if (!weighted) lane_walk<kFoUnw, uint32_t>(a, w);
-    else if (r64) lane_walk<kFoW, uint64_t>(a, w);
-    else lane_walk<kFoW, uint32_t>(a, w);
+    if (!weighted) lane_walk<kFoUnw, uint32_t>(a, w, st);
+    else if (r64) lane_walk<kFoW, uint64_t>(a, w, st);
+    else lane_walk<kFoW, uint32_t>(a, w, st);
   } else {
-    if (!weighted) lane_walk<kRetUnw, uint32_t>(a, w);
-    else if (r64) lane_walk<kRetW, uint64_t>(a, w);
-    else lane_walk<kRetW, uint32_t>(a, w);
+    if (!weighted) lane_walk<kRetUnw, uint32_t>(a, w, st);
+    else if (r64) lane_walk<kRetW, uint64_t>(a, w, st);
+    else lane_walk<kRetW, uint32_t>(a, w, st);
   }
 }
 
@@ -1285,23 +1339,28 @@ __global__ __launch_bounds__(256, G == 64 ? 7 : (G == 4 ? (LISTS ? 7 : 5) : 1)) 
   extern __shared__ int32_t lds[];
   constexpr uint32_t GPW = 64 / G;
   const int lane = threadIdx.x & 63;
-  const int gib = threadIdx.x / G;
   const uint32_t giw = (uint32_t)lane / G;  // group index within the wavefront
-  int32_t* const mem = lds + (size_t)gib * group_lds_words(tile, cap, G);
+  // the wavefront's LDS: its groups' regions, or its lanes' output stages
+  int32_t* const wmem = lds + (size_t)(threadIdx.x / 64u) * queue_wave_words(tile, cap, G);
+  int32_t* const mem = wmem + (size_t)giw * group_lds_words(tile, cap, G);
+  int32_t* const st = wmem + lane;
   while (true) {
     uint32_t c = 0;
     if (lane == 0) c = atomicAdd(head, 1u);
     c = (uint32_t)__builtin_amdgcn_readlane((int)c, 0);
     if (c >= nchunks) break;  // every wavefront exits once the queue is drained
+    // the previous chunk's LDS reads by other lanes come before this chunk's writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const QueueChunk ch = chunks[c];
     const WalkArgs a = from_global(((const WalkArgsG*)reqs)[ch.req]);
     if (a.path != (uint32_t)Path::kGeneric) {
       for (uint64_t w = ch.w0 + (uint64_t)lane; w < ch.w1; w += 64) {
         if constexpr (W32) {
-          if (a.path == (uint32_t)Path::kFirstOrder) lane_walk<kFoW, uint32_t>(a, w);
-          else lane_walk<kRetW, uint32_t>(a, w);
+          if (a.path == (uint32_t)Path::kFirstOrder) lane_walk<kFoW, uint32_t>(a, w, st);
+          else lane_walk<kRetW, uint32_t>(a, w, st);
         } else {
-          lane_dispatch<G>(a, w);
+          lane_dispatch<G>(a, w, st);
         }
       }
     } else if (W32) {
@@ -1459,7 +1518,7 @@ hipError_t go_queue(const WalkArgs* reqs, const QueueChunk* chunks, uint32_t nch
   const int gpb = 256 / G;
   const bool lists = queue_lists(cfg);
   const int tile = lists ? 0 : cfg.lds_tile, cap = lists ? 0 : cfg.list_cap;
-  const size_t lds = (size_t)gpb * group_lds_words(tile, cap, G) * sizeof(int32_t);
+  const size_t lds = 4 * (size_t)queue_wave_words(tile, cap, G) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, ((uint64_t)nchunks + gpb - 1) / gpb, di);
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, head);
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, reqs, chunks, nchunks, head, tile, cap, cfg.mode);
@@ -1472,7 +1531,7 @@ int queue_grid_blocks(const LaunchCfg& cfg, const DevInfo& di, uint32_t nchunks)
   const int G = cfg.lanes_per_walker == 4 ? 4 : (cfg.lanes_per_walker == 16 ? 16 : (cfg.lanes_per_walker == 32 ? 32 : 64));
   const int gpb = 256 / G;
   const bool lists = queue_lists(cfg);
-  const size_t lds = (size_t)gpb * group_lds_words(lists ? 0 : cfg.lds_tile, lists ? 0 : cfg.list_cap, G) * sizeof(int32_t);
+  const size_t lds = 4 * (size_t)queue_wave_words(lists ? 0 : cfg.lds_tile, lists ? 0 : cfg.list_cap, G) * sizeof(int32_t);
   const uint64_t work = ((uint64_t)nchunks + gpb - 1) / gpb;
   if (G == 4) return grid_for(queue_kernel<4>(cfg), lds, work, di);
   if (G == 16) return grid_for(queue_kernel<16>(cfg), lds, work, di);
