@@ -434,6 +434,13 @@ struct CtxArgs {
 template <int G, bool WEIGHTED, typename RT, bool FULL, bool HEADS = false, bool CTX = false, bool LISTS = false>
 __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_t* mem, int tile, int cap,
                                            int mode_knob, const CtxArgs& cx = CtxArgs{}) {
+  if constexpr (LISTS) {
+    // the lists-only variant stages no row and builds no list: said at
+    // compile time, the staging code and its state drop out
+    tile = 0;
+    cap = 0;
+    mode_knob = kModeAuto;
+  }
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);

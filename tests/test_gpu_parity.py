@@ -201,8 +201,11 @@ def test_hub_pair_lists_identical():
     assert i1["pair_lists"] > 1000 and i1["pair_entries"] > 0
     assert i0["pair_lists"] == 0 and i0["pair_entries"] == 0
     starts = np.arange(n)
-    # two walks per node: 40,000 walks, enough for the 4-lane groups that
-    # serve graphs whose edges all keep a list
+    # on this graph the lists of only part of the edges fit the budget, so the
+    # walks take one wavefront each and use the routes where no list is kept
+    # (test_automatic_four_lane_lists_only covers the graphs whose edges all
+    # keep one)
+    assert i1["pair_lists"] < len(D)
     rows = np.arange(0, 2 * n, 57)
     for p, q in ((0.25, 4.0), (2.0, 0.5), (1.0, 2.0), (4.0, 0.25)):
         Y1, L1 = run(g1, starts, 2, 40, NV, p, q, seed=8)
@@ -212,6 +215,32 @@ def test_hub_pair_lists_identical():
         assert np.array_equal(Y1[rows], Yo) and np.array_equal(L1[rows], lo), (p, q)
     n2v.n2v_graph_release(g0)
     n2v.n2v_graph_release(g1)
+
+
+def test_automatic_four_lane_lists_only():
+    """Every edge keeps its stored list and the launch has at least 96 walks per
+    CU: the automatic shape is then 4-lane groups of the lists-only variant.
+    Its walks equal those of a handle without lists (the list-building routes)
+    and the oracle's, for in-out biases on both sides of 1."""
+    O, D, W = synth.chung_lu(20000, 200000, 2.2, 20.0, 2000.0, (1, 100), seed=31)
+    n = len(O) - 1
+    g1, k1 = upload(O, D, W)
+    Ot, Dt, Wt = k1
+    g0 = n2v.n2v_graph_upload(Ot, Dt, Wt, flags=n2v.N2V_UPLOAD_NO_PAIR_LISTS)
+    assert n2v.n2v_graph_info(g1)["pair_lists"] == len(D)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    reps = -(-96 * cus // n)  # walks per node for at least 96 walks per CU
+    starts = np.arange(n)
+    rows = np.arange(0, reps * n, 97)
+    for p, q in ((0.25, 4.0), (2.0, 0.5), (1.0, 2.0)):
+        Y1, L1 = run(g1, starts, reps, 40, NV, p, q, seed=12)
+        Y0, L0 = run(g0, starts, reps, 40, NV, p, q, seed=12)
+        assert np.array_equal(Y1, Y0) and np.array_equal(L1, L0), (p, q)
+        Yo, lo = oracle.walks(O, D, W, starts, reps, 40, NV, p, q, 12, 0, rows=rows)
+        assert np.array_equal(Y1[rows], Yo) and np.array_equal(L1[rows], lo), (p, q)
+    n2v.n2v_graph_release(g0)
+    n2v.n2v_graph_release(g1)
+    del k1
 
 
 def test_edge_lists_over_budget():
