@@ -214,7 +214,8 @@ __global__ __launch_bounds__(256) void k_edge_info(const uint4* __restrict__ mea
   for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
     const uint4 me = meas[e];
     const bool k = !keep || keep[e];
-    info[2 * e] = k ? make_uint4((uint32_t)off[e], me.x, me.y, me.z) : make_uint4(0xFFFFFFFFu, 0u, 0u, 0u);
+    // t's position in N(v) stays in an edge without a list (return-only steps read it)
+    info[2 * e] = k ? make_uint4((uint32_t)off[e], me.x, me.y, me.z) : make_uint4(0xFFFFFFFFu, 0u, me.y, 0u);
     info[2 * e + 1] = make_uint4(me.w, 0u, 0u, 0u);
     kept += k ? 1u : 0u;
     if (e == m - 1) tot[1] = off[e] + (k ? me.x : 0u);

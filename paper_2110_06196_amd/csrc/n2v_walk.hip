@@ -95,6 +95,7 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w, int32_t
       put(0, start);
       len = 1;
       int32_t v = start, t = -1;
+      uint64_t epos = 0;  // position of the edge t -> v in the entries
       for (uint32_t s = 1; s < a.L; ++s) {
         uint64_t lo;
         uint32_t d;
@@ -119,11 +120,20 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w, int32_t
           if (total == 0) break;  // every candidate has weight zero
           j = upper_bound_interp(R + lo, d, scale_draw(r, total), total);
         } else {
-          int32_t vt;
-          const uint32_t pt = floor_search(D + lo, 0u, d, D[lo], t, vt);
-          const bool has_t = vt == t;
+          uint32_t pt;
           uint64_t wt = 0;
-          if (has_t) wt = (MODE == kRetW) ? (uint64_t)a.g.W[lo + pt] : 1ull;
+          if (kRec && MODE == kRetW && a.g.pair_info != nullptr) {
+            // the 32-byte record of the edge t -> v (built at upload for every
+            // edge) holds t's position in N(v), all ones when t is not a
+            // neighbour of v, and t's weight there (0): read beside the node
+            // record instead of a search of N(v) for t
+            pt = a.g.pair_info[2 * epos].z;
+            wt = a.g.pair_info[2 * epos + 1].x;
+          } else {
+            int32_t vt;
+            pt = floor_search(D + lo, 0u, d, D[lo], t, vt);
+            if (vt == t) wt = (MODE == kRetW) ? (uint64_t)a.g.W[lo + pt] : 1ull;
+          }
           const uint64_t S =
               (MODE == kRetW) ? ((kRec && a.g.NR) ? rowsum : (uint64_t)R[lo + d - 1]) : (uint64_t)d;
           const uint64_t corr = ((uint64_t)a.P16 - (uint64_t)kC16) * wt;  // mod 2^64
@@ -145,6 +155,7 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w, int32_t
         len = s + 1;
         t = v;
         v = x;
+        epos = lo + j;
       }
     }
     // staged slots [s0, len) (the start of len's line, or 0), then the padding
