@@ -140,15 +140,12 @@ __device__ __forceinline__ void lane_walk(const WalkArgs& a, uint64_t w, int32_t
           const uint64_t total = (uint64_t)kC16 * S + corr;
           if (total == 0) break;
           const uint64_t T = scale_draw(r, total);
-          uint32_t jl = 0, jh = d - 1;
-          while (jl < jh) {
-            const uint32_t mid = jl + ((jh - jl) >> 1);
-            const uint64_t Rm = (MODE == kRetW) ? (uint64_t)R[lo + mid] : (uint64_t)(mid + 1);
-            const uint64_t Bm = (uint64_t)kC16 * Rm + (mid >= pt ? corr : 0ull);
-            if (Bm > T) jh = mid;
-            else jl = mid + 1;
-          }
-          j = jl;
+          // B_m = C16 R_m (+ corr from t's position on): the row prefix scaled
+          // and shifted at one position, searched like the first-order prefix
+          j = first_above_interp(d, T, total, [&](uint32_t m) -> uint64_t {
+            const uint64_t Rm = (MODE == kRetW) ? (uint64_t)R[lo + m] : (uint64_t)(m + 1);
+            return (uint64_t)kC16 * Rm + (m >= pt ? corr : 0ull);
+          });
         }
         const int32_t x = D[lo + j];
         put(s, x);
