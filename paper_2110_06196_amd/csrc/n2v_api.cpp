@@ -771,6 +771,7 @@ int n2v_walks_contexts(n2v_graph g, uint32_t kind, const int32_t* d_starts, uint
   uint32_t rp = 1;
   while (rp < 2 * hh + 1) rp <<= 1;
   LaunchCfg cfg = choose_cfg(*gr, di, a.nwalks);
+  cfg.lists = gr->pair_lists > 0 && gr->pair_lists == gr->n_entries ? 1 : 0;
   // groups of 4, 16 or 64 lanes (the narrowest at or above the chosen width)
   // whose block, rings included, fits the LDS
   cfg.lanes_per_walker = cfg.lanes_per_walker <= 4 ? 4 : (cfg.lanes_per_walker <= 16 ? 16 : 64);

@@ -1203,9 +1203,9 @@ __global__ __launch_bounds__(256, G == 64 ? 8 : (G == 4 ? (LISTS ? 7 : 5) : (G =
 // Fused walk -> contexts: the node2vec kernel's walker loop with context
 // output (every kind runs through the group routine: its first-order branch
 // serves first-order walks and the first step of node2vec walks).
-template <int G, bool WEIGHTED, typename RT>
-__global__ __launch_bounds__(256) void k_walk_ctx(WalkArgs a, int tile, int cap, CtxArgs cx, unsigned long long* ctr,
-                                                  uint32_t chunk) {
+template <int G, bool WEIGHTED, typename RT, bool LISTS = false>
+__global__ __launch_bounds__(256, LISTS ? 7 : 1) void k_walk_ctx(WalkArgs a, int tile, int cap, CtxArgs cx,
+                                                                  unsigned long long* ctr, uint32_t chunk) {
   extern __shared__ int32_t lds[];
   const int gib = G == 64 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x / 64u) : (int)(threadIdx.x / G);
   const int gpb = blockDim.x / G;
@@ -1223,7 +1223,7 @@ __global__ __launch_bounds__(256) void k_walk_ctx(WalkArgs a, int tile, int cap,
       }
     }
     if (w >= a.nwalks) break;
-    group_walk<G, WEIGHTED, RT, false, false, true>(a, w, mem, tile, cap, kModeAuto, cx);
+    group_walk<G, WEIGHTED, RT, false, false, true, LISTS>(a, w, mem, tile, cap, kModeAuto, cx);
     w += ctr ? 1 : ngroups;
   }
 }
@@ -1568,12 +1568,17 @@ hipError_t launch_queue(const WalkArgs* d_reqs, const QueueChunk* d_chunks, uint
 namespace {
 template <int G, bool WEIGHTED, typename RT>
 hipError_t go_ctx(const WalkArgs& a, const LaunchCfg& cfg, const CtxArgs& cx, const DevInfo& di, hipStream_t st) {
-  auto k = k_walk_ctx<G, WEIGHTED, RT>;
+  // 4-lane groups on graphs whose edges all keep a stored list (automatic
+  // route): the lists-only variant, as for the walk kernel
+  constexpr bool kL = G == 4 && WEIGHTED && sizeof(RT) == 4;
+  const bool lists = kL && cfg.lists && cfg.mode == kModeAuto;
+  auto k = lists ? k_walk_ctx<G, WEIGHTED, RT, kL> : k_walk_ctx<G, WEIGHTED, RT>;
   const int gpb = 256 / G;
-  const size_t lds = (size_t)gpb * (group_lds_words(cfg.lds_tile, cfg.list_cap, G) + cx.rp) * sizeof(int32_t);
+  const int tile = lists ? 0 : cfg.lds_tile, cap = lists ? 0 : cfg.list_cap;
+  const size_t lds = (size_t)gpb * (group_lds_words(tile, cap, G) + cx.rp) * sizeof(int32_t);
   int blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : grid_for(k, lds, (a.nwalks + gpb - 1) / gpb, di);
   return with_walk_counter(di, st, [&](unsigned long long* ctr) {
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, cfg.lds_tile, cfg.list_cap, cx, ctr,
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a, tile, cap, cx, ctr,
                        walk_chunk(a.nwalks, (uint64_t)blocks * gpb));
     return hipGetLastError();
   });

@@ -72,6 +72,24 @@ def test_power_law_all_group_widths(lanes):
     del keep
 
 
+def test_automatic_four_lane_lists_only():
+    """Every edge keeps its stored list and the launch has at least 96 walks per
+    CU: the fused kernel's automatic shape is 4-lane groups of the lists-only
+    variant; its contexts equal those of the materialised walks and the
+    oracle's."""
+    O, D, W = synth.chung_lu(20000, 200000, 2.2, 20.0, 2000.0, (1, 100), seed=31)
+    n = len(O) - 1
+    g, keep = upload(O, D, W)
+    assert n2v.n2v_graph_info(g)["pair_lists"] == len(D)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    reps = -(-96 * cus // n)
+    starts = np.arange(n, dtype=np.int32)
+    for kind, p, q in ((NV, 0.25, 4.0), (NV, 2.0, 1.0), (FO, 1.0, 1.0)):
+        _check(g, O, D, W, starts, reps, 20, kind, p, q, 19, 0, 5, 1)
+    n2v.n2v_graph_release(g)
+    del keep
+
+
 def test_errors():
     O, D, W = synth.TINY["tri_tail"]()
     g, keep = upload(O, D, W)
