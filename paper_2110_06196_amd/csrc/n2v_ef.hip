@@ -18,26 +18,36 @@ namespace n2v {
 namespace {
 
 // Bit position of set bit number r (from 0, least significant first) of b,
-// which has more than r set bits: a popcount bisection over halves.
+// which has more than r set bits: a popcount bisection over halves (the word
+// half first, then 32-bit arithmetic).
 __device__ __forceinline__ uint32_t nth_set_bit(uint64_t b, uint32_t r) {
-  uint32_t pos = 0;
-  uint32_t c = (uint32_t)__popcll(b & 0xFFFFFFFFull);
-  if (r >= c) { r -= c; b >>= 32; pos += 32; }
-  c = (uint32_t)__popcll(b & 0xFFFFull);
-  if (r >= c) { r -= c; b >>= 16; pos += 16; }
-  c = (uint32_t)__popcll(b & 0xFFull);
-  if (r >= c) { r -= c; b >>= 8; pos += 8; }
-  c = (uint32_t)__popcll(b & 0xFull);
-  if (r >= c) { r -= c; b >>= 4; pos += 4; }
-  c = (uint32_t)__popcll(b & 0x3ull);
-  if (r >= c) { r -= c; b >>= 2; pos += 2; }
-  if (r >= (uint32_t)(b & 1ull)) pos += 1;
+  uint32_t x = (uint32_t)b, pos = 0;
+  uint32_t c = (uint32_t)__popc(x);
+  if (r >= c) { r -= c; x = (uint32_t)(b >> 32); pos = 32; }
+  c = (uint32_t)__popc(x & 0xFFFFu);
+  if (r >= c) { r -= c; x >>= 16; pos += 16; }
+  c = (uint32_t)__popc(x & 0xFFu);
+  if (r >= c) { r -= c; x >>= 8; pos += 8; }
+  c = (uint32_t)__popc(x & 0xFu);
+  if (r >= c) { r -= c; x >>= 4; pos += 4; }
+  c = (uint32_t)__popc(x & 0x3u);
+  if (r >= c) { r -= c; x >>= 2; pos += 2; }
+  if (r >= (x & 1u)) pos += 1;
   return pos;
 }
 
 __device__ __forceinline__ uint64_t ef_low(const EFDev& e, uint64_t i) {
   if (e.l == 0) return 0;
   const uint64_t bit = i * e.l;
+  if (e.l <= 32) {
+    // the field lies inside the 64 bits from the 32-bit word holding its first
+    // bit: two word loads side by side and one funnel shift, no branch (the
+    // word after L's last is S1's first, inside the same allocation)
+    const uint32_t* __restrict__ L32 = reinterpret_cast<const uint32_t*>(e.L);
+    const uint64_t w32 = bit >> 5;
+    const uint32_t v = __builtin_amdgcn_alignbit(L32[w32 + 1], L32[w32], (uint32_t)bit & 31u);
+    return e.l == 32 ? (uint64_t)v : (uint64_t)(v & ((1u << e.l) - 1u));
+  }
   const uint64_t w = bit >> 6;
   const uint32_t o = (uint32_t)(bit & 63);
   uint64_t v = e.L[w] >> o;

@@ -243,6 +243,39 @@ def test_automatic_four_lane_lists_only():
     del k1
 
 
+@pytest.mark.parametrize("off", [1, 6, 15])
+def test_output_rows_at_any_alignment(off):
+    """Walk rows leave in whole 64-byte lines chosen by address: an output array
+    that starts `off` words into a line shifts every row's phase.  The walks
+    equal those written to an aligned array, and nothing before or after the
+    array is written (lane kernels, 4-, 16- and 64-lane groups, dead ends)."""
+    O, D, W = synth.chung_lu(3000, 30000, 2.2, 12.0, 400.0, (1, 100), seed=13)
+    n = len(O) - 1
+    assert (np.diff(O) == 0).any()  # some starts are dead ends: their rows are padding
+    g, keep = upload(O, D, W)
+    S = torch.arange(n, dtype=torch.int32, device="cuda")
+    L, reps = 37, 2
+    nw = n * reps
+    for lanes in (0, 4, 16, 64):
+        n2v.n2v_set_tuning(reset=True) if lanes == 0 else n2v.n2v_set_tuning(lanes_per_walker=lanes)
+        for kind, p, q in ((FO, 1.0, 1.0), (NV, 4.0, 1.0), (NV, 0.25, 4.0), (NV, 2.0, 0.5)):
+            flat = torch.full((nw * L + off + 16,), -7, dtype=torch.int32, device="cuda")
+            Y = flat[off:off + nw * L].view(nw, L)
+            lens = torch.empty(nw, dtype=torch.int32, device="cuda")
+            if kind == FO:
+                ref, rl = n2v.n2v_walks_first_order(g, S, reps, L, 23)
+                n2v.n2v_walks_first_order(g, S, reps, L, 23, walks=Y, lens=lens)
+            else:
+                ref, rl = n2v.n2v_walks_node2vec(g, S, reps, L, p, q, 23)
+                n2v.n2v_walks_node2vec(g, S, reps, L, p, q, 23, walks=Y, lens=lens)
+            torch.cuda.synchronize()
+            assert torch.equal(Y, ref) and torch.equal(lens, rl), (lanes, kind, p, q)
+            assert bool((flat[:off] == -7).all()) and bool((flat[off + nw * L:] == -7).all()), (lanes, kind, p, q)
+    n2v.n2v_set_tuning(reset=True)
+    n2v.n2v_graph_release(g)
+    del keep
+
+
 def test_edge_lists_over_budget():
     """A complete graph has n - 2 common neighbours on every edge, more than the
     lists' budget of 16 entries per graph entry: only part of the edges keep a
