@@ -464,6 +464,107 @@ __device__ __forceinline__ uint64_t ef_decode_chunk(const EFDev& e, uint64_t i0,
   return code;
 }
 
+// Positions of zeros z0 .. z0 + cnt - 1 of H (cnt <= 64, zero z0 + cnt - 1
+// exists), lane j getting zero z0 + j (other lanes: unspecified).  From the
+// quantum sample at or before z0 the wavefront reads 64 words of H at a time,
+// counts their zeros (a wave scan), and each lane finds the word of its zero
+// by a bisection over the lanes' counts and its bit by a popcount bisection:
+// one round per 4096 bits, where a one-lane select scans word by word.
+__device__ __forceinline__ uint64_t wave_zero_positions(const EFDev& e, uint64_t z0, uint32_t cnt, int gl) {
+  const uint64_t js = z0 >> e.lgq;
+  const uint64_t p = e.S0[js];  // position of zero js 2^lgq
+  const uint32_t skip = (uint32_t)(z0 - (js << e.lgq));
+  const uint32_t want = skip + (uint32_t)gl;  // this lane's zero, counted from the one at p
+  const uint32_t last = skip + cnt - 1u;
+  const uint64_t hw = (e.h_bits + 63) >> 6;
+  const uint32_t tail = (uint32_t)(e.h_bits & 63);
+  uint64_t w0 = p >> 6;
+  uint64_t mask0 = ~0ull << (p & 63);
+  uint32_t got = 0;
+  uint64_t mine = 0;
+  while (got <= last) {
+    const uint64_t wi = w0 + (uint64_t)gl;
+    uint64_t word = 0;
+    if (wi < hw) {
+      word = ~e.H[wi] & (gl == 0 ? mask0 : ~0ull);
+      if (wi == hw - 1 && tail) word &= (1ull << tail) - 1;  // no zeros past the end of H
+    }
+    const uint32_t incl = wave_incl_scan_u32((uint32_t)__popcll(word));
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const uint32_t r = want - got;
+    const bool here = (uint32_t)gl < cnt && want >= got && r < total;
+    int lo = 0, hi = 63;  // first lane whose inclusive count exceeds r
+    for (int it = 0; it < 6; ++it) {
+      const int mid = (lo + hi) >> 1;
+      const uint32_t cm = (uint32_t)__shfl((int)incl, mid, 64);
+      if (cm > r) hi = mid;
+      else lo = mid + 1;
+    }
+    const uint32_t cL = (uint32_t)__shfl((int)incl, lo, 64);
+    const uint32_t wlo = (uint32_t)__shfl((int)(uint32_t)word, lo, 64);
+    const uint32_t whi = (uint32_t)__shfl((int)(uint32_t)(word >> 32), lo, 64);
+    if (here) {
+      const uint64_t wL = (uint64_t)wlo | ((uint64_t)whi << 32);
+      mine = ((w0 + (uint64_t)lo) << 6) + nth_set_bit(wL, r - (cL - (uint32_t)__popcll(wL)));
+    }
+    got += total;
+    w0 += 64;
+    mask0 = ~0ull;
+  }
+  return mine;
+}
+
+// When a row spans nb = 2^(k - l) < 64 buckets of high parts (l <= k), the
+// wavefront keeps the row's bucket boundaries: lane j <= nb holds the position
+// of zero hx0 - 1 + j, hx0 = v nb (-1 for the zero before H when v = 0).  The
+// row is [zb_0 - (hx0 - 1), zb_nb - (hx0 + nb - 1)), and bucket b holds the
+// codes [zb_b + 1 - (hx0 + b), +(zb_(b+1) - zb_b - 1)).  One cooperative
+// decode per step replaces the word-by-word zero scans of every rank into the
+// row (a hub's row spans thousands of words).
+__device__ __forceinline__ int64_t ef_row_bounds(const EFDev& e, int32_t v, uint32_t nb, int gl, uint64_t* lo,
+                                                 uint32_t* d) {
+  const uint64_t hx0 = (uint64_t)(uint32_t)v * nb;
+  int64_t zb;
+  if (hx0 > 0) {
+    zb = (int64_t)wave_zero_positions(e, hx0 - 1, nb + 1, gl);
+  } else {
+    const int64_t z = (int64_t)wave_zero_positions(e, 0, nb, gl);  // lane j: zero j
+    const int src = gl > 0 ? gl - 1 : 0;
+    const int64_t zs = (int64_t)(((uint64_t)(uint32_t)__shfl((int)(uint32_t)((uint64_t)z >> 32), src, 64) << 32) |
+                                 (uint64_t)(uint32_t)__shfl((int)(uint32_t)(uint64_t)z, src, 64));
+    zb = gl == 0 ? -1 : zs;
+  }
+  const int64_t z0 = (int64_t)wave_read_u64((uint64_t)zb, 0);
+  const int64_t z1 = (int64_t)wave_read_u64((uint64_t)zb, (int)nb);
+  *lo = (uint64_t)(z0 + 1) - hx0;
+  *d = (uint32_t)(((uint64_t)(z1 + 1) - (hx0 + nb)) - *lo);
+  return zb;
+}
+
+// The boundaries of bucket b of the row whose boundaries the lanes hold (every
+// lane of the wavefront takes part: call from uniform control flow).
+__device__ __forceinline__ void ef_bucket_of(int64_t zb, uint32_t b, int64_t* za, int64_t* zc) {
+  auto rd = [&](uint32_t src) {
+    return (int64_t)(((uint64_t)(uint32_t)__shfl((int)(uint32_t)((uint64_t)zb >> 32), (int)src, 64) << 32) |
+                     (uint64_t)(uint32_t)__shfl((int)(uint32_t)(uint64_t)zb, (int)src, 64));
+  };
+  *za = rd(b);
+  *zc = rd(b + 1);
+}
+
+// rank of the code hx0 2^l + y' (y' = y, a node id) inside its row, from the
+// bucket boundaries za, zc of its bucket b = y >> l, and whether it is present.
+__device__ __forceinline__ uint64_t ef_rank_in_bucket(const EFDev& e, uint64_t hx0, uint32_t y, int64_t za,
+                                                      int64_t zc, bool* has) {
+  const uint32_t b = y >> e.l;
+  const uint64_t xl = e.l ? ((uint64_t)y & ((1ull << e.l) - 1)) : 0;
+  const uint64_t i = (uint64_t)(za + 1) - (hx0 + b);
+  const uint64_t c = (uint64_t)(zc - za - 1);
+  const uint64_t j = xl == 0 ? i : ef_low_bound(e, i, c, xl);
+  *has = j < i + c && ef_low(e, j) == xl;
+  return j;
+}
+
 // First j in [lo, hi) with pred(j) (monotone), or hi: 64 evenly spaced
 // probes per round across the wavefront.
 template <typename P>
@@ -505,7 +606,13 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
     uint64_t tlo = 0;
     uint64_t lo;
     uint32_t dnext;
-    ef_row(e, v, &lo, &dnext);
+    // bucket boundaries of the rows of v and t (lanes 0 .. nb), when a row
+    // spans fewer than 64 buckets
+    const bool use_b = e.l <= e.k && e.k - e.l < 6;
+    const uint32_t nb = use_b ? 1u << (e.k - e.l) : 0u;
+    int64_t vb = 0, tb = 0;
+    if (use_b) vb = ef_row_bounds(e, v, nb, gl, &lo, &dnext);
+    else ef_row(e, v, &lo, &dnext);
     const uint64_t lt_mask = gl == 0 ? 0ull : (~0ull >> (64 - gl));
     auto Rv = [&](uint32_t j) -> uint64_t { return WEIGHTED ? (uint64_t)R[lo + j] : (uint64_t)j + 1ull; };
     // lane gl holds the draw of step s1 + gl: one vector Philox evaluation
@@ -569,7 +676,13 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
             uint32_t pos = 0;
             int32_t y = t;
             if (k < td) y = t_in_lds ? cur[k] : ef_nbr(e, tlo + k);
-            if (k <= td) pos = (uint32_t)(ef_rank_has(e, vc0 | (uint64_t)(uint32_t)y, &hit) - lo);
+            if (use_b) {
+              int64_t za, zc;
+              ef_bucket_of(vb, (uint32_t)y >> e.l, &za, &zc);
+              if (k <= td) pos = (uint32_t)(ef_rank_in_bucket(e, (uint64_t)(uint32_t)v * nb, (uint32_t)y, za, zc, &hit) - lo);
+            } else if (k <= td) {
+              pos = (uint32_t)(ef_rank_has(e, vc0 | (uint64_t)(uint32_t)y, &hit) - lo);
+            }
             const uint64_t mt = grp_ballot<G>(hit && tkey, 0);
             if (mt) {
               has_t = true;
@@ -605,8 +718,16 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
               has_t = true;
               pt = c + (uint32_t)(__ffsll((unsigned long long)mt) - 1);
             }
-            const bool common =
-                act && !isret && (t_in_lds ? lds_has(cur, td, x) : ef_contains(e, tc0 | (uint64_t)(uint32_t)x));
+            bool common;
+            if (!t_in_lds && use_b) {
+              int64_t za, zc;
+              ef_bucket_of(tb, (uint32_t)x >> e.l, &za, &zc);
+              bool h = false;
+              if (act && !isret) (void)ef_rank_in_bucket(e, (uint64_t)(uint32_t)t * nb, (uint32_t)x, za, zc, &h);
+              common = act && !isret && h;
+            } else {
+              common = act && !isret && (t_in_lds ? lds_has(cur, td, x) : ef_contains(e, tc0 | (uint64_t)(uint32_t)x));
+            }
             const uint64_t m = grp_ballot<G>(common, 0);
             if (common) {
               cw += WEIGHTED ? weight_at(R, lo, j) : 1ull;
@@ -729,7 +850,9 @@ __device__ __forceinline__ void wave_walk_ef(const WalkArgs& a, const EFDev& e, 
         nxt = tmp;
       }
       v = x;
-      ef_row(e, v, &lo, &dnext);
+      tb = vb;
+      if (use_b) vb = ef_row_bounds(e, v, nb, gl, &lo, &dnext);
+      else ef_row(e, v, &lo, &dnext);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
