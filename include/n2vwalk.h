@@ -29,7 +29,9 @@
  *     CUDA tensors); "host pointer" means ordinary CPU memory;
  *   - hip_stream is a hipStream_t passed as void* (NULL = default stream).
  *
- * Walk output layout: walks is int32[n_walks][walk_len], row-major, with
+ * Walk output layout: walks is int32[n_walks][walk_len] (1 <= walk_len <= 2^30),
+ * row-major, 4-byte aligned (rows are stored in whole 64-byte lines where the
+ * address allows), with
  * n_walks = walks_per_start * n_starts and row w = rep * n_starts + i using
  * start starts[i] and walk id walk_id_base + w.  Slot 0 holds the start; a walk
  * that reaches a node with no out-edge (or whose candidates all have weight
@@ -48,7 +50,7 @@ extern "C" {
 enum {
   N2V_OK = 0,
   N2V_PENDING = 1,          /* n2v_request_poll: not finished yet (not an error) */
-  N2V_ERR_INVALID_ARG = -1, /* NULL pointer, zero size where one is needed, walk_len == 0,
+  N2V_ERR_INVALID_ARG = -1, /* NULL pointer, zero size where one is needed, walk_len == 0 or > 2^30,
                                walks_per_start == 0, p or q not finite and > 0, or their
                                Q16 value outside [1, 2^32-1] */
   N2V_ERR_UNSORTED = -2,    /* offsets[0] != 0, offsets not monotone, offsets[n] != n_entries,

@@ -170,6 +170,8 @@ int prepare_request(const GraphRec& gr, uint32_t kind, const int32_t* d_starts, 
                     uint64_t walk_id_base, int32_t* d_walks, int32_t* d_lens, uint32_t k_approx,
                     WalkArgs* a, Path* path) {
   if (walk_len == 0) return fail(N2V_ERR_INVALID_ARG, "walk_len must be >= 1");
+  // lengths are int32 and the kernels index a row's slots in 32-bit arithmetic
+  if (walk_len > (1u << 30)) return fail(N2V_ERR_INVALID_ARG, "walk_len %u above 2^30", walk_len);
   if (walks_per_start == 0) return fail(N2V_ERR_INVALID_ARG, "walks_per_start must be >= 1");
   if (kind != N2V_FIRST_ORDER && kind != N2V_NODE2VEC) return fail(N2V_ERR_INVALID_ARG, "bad kind");
   if (n_starts > 0 && (!d_starts || !d_walks))

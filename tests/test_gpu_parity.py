@@ -336,6 +336,13 @@ def test_errors():
         assert e.value.code == n2v.N2V_ERR_INVALID_ARG
     with pytest.raises(n2v.N2VError):
         run(g, [0], 1, 0, FO)
+    # walk_len above 2^30 is refused before any device work (no output is touched)
+    S1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Y1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert n2v.lib().n2v_walks_first_order(g, S1.data_ptr(), 1, 1, 2**30 + 1, 0, 0, Y1.data_ptr(), None,
+                                           None) == n2v.N2V_ERR_INVALID_ARG
+    assert n2v.lib().n2v_walks_node2vec(g, S1.data_ptr(), 1, 1, 2**30 + 1, 1.0, 2.0, 0, 0, Y1.data_ptr(), None,
+                                        None) == n2v.N2V_ERR_INVALID_ARG
     # overflow precondition
     O5, D5, _ = synth.star(70000)
     W5 = np.full(D5.size, 2**30, dtype=np.uint32)
