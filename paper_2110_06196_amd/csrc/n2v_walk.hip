@@ -786,7 +786,12 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
               const uint64_t stream = (uint64_t)((d + G - 1) / G) *
                                           (100u + (t_in_lds ? 15u * ceil_log2p1(td) : glob(td))) +
                                       (!t_in_lds && td >= 4u * G ? 100u : 0u);
-              const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) * (t_in_lds ? 150u : 240u);
+              // a merge round streams two lines where a probe round of G keys
+              // reads G random lines per level: besides its latency, the
+              // merge is priced for the traffic it saves (measured on a
+              // 20M-node graph with 1.25M-entry rows: a round at 240 -> 60
+              // took node2vec (1, 2) from 21.6 to 14.4 s; 30 gave 14.5, 15 18.1)
+              const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) * (t_in_lds ? 40u : 60u);
               mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
                                     : (stream <= merge ? kModeStream : kModeMerge);
               if constexpr (HEADS) {
