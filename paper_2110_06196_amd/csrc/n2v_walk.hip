@@ -787,11 +787,16 @@ __device__ __forceinline__ void group_walk(const WalkArgs& a, uint64_t w, int32_
                                           (100u + (t_in_lds ? 15u * ceil_log2p1(td) : glob(td))) +
                                       (!t_in_lds && td >= 4u * G ? 100u : 0u);
               // a merge round streams two lines where a probe round of G keys
-              // reads G random lines per level: besides its latency, the
-              // merge is priced for the traffic it saves (measured on a
-              // 20M-node graph with 1.25M-entry rows: a round at 240 -> 60
-              // took node2vec (1, 2) from 21.6 to 14.4 s; 30 gave 14.5, 15 18.1)
-              const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) * (t_in_lds ? 40u : 60u);
+              // reads G random lines per level: once the two rows are too long
+              // for the caches to hold them (2^14 entries together), the merge
+              // is priced for the traffic it saves (measured on a 20M-node
+              // graph with 1.25M-entry rows: a round at 240 -> 60 took node2vec
+              // (1, 2) from 21.6 to 14.4 s; 30 gave 14.5, 15 gave 18.1; without
+              // the length gate the 64-graph plan without stored lists lost 12%,
+              // and a gate at 2^16 gave 18.4 s)
+              const bool uncached = (uint64_t)d + td >= (1u << 14);
+              const uint64_t merge = (uint64_t)(((uint64_t)d + td + 2u * G - 1) / (2u * G)) *
+                                     (uncached ? (t_in_lds ? 40u : 60u) : (t_in_lds ? 150u : 240u));
               mode = probe < stream ? (probe <= merge ? kModeProbe : kModeMerge)
                                     : (stream <= merge ? kModeStream : kModeMerge);
               if constexpr (HEADS) {
