@@ -36,6 +36,32 @@ __device__ __forceinline__ uint32_t nth_set_bit(uint64_t b, uint32_t r) {
   return pos;
 }
 
+// From word w of H whose wanted bits (ones, or zeros when ZEROS) below the
+// start are already masked out of b, the word holding wanted bit number r and
+// that bit's position, reading two words per round (both loads in flight).
+// The word after H's last lies in the same allocation (L, S1 or S0 follow),
+// and the wanted bit always lies inside H, so the read ahead stays in bounds.
+template <bool ZEROS>
+__device__ __forceinline__ uint64_t ef_scan(const uint64_t* __restrict__ H, uint64_t w, uint64_t b, uint64_t r) {
+  while (true) {
+    const uint32_t c = (uint32_t)__popcll(b);
+    if (r < c) break;
+    r -= c;
+    const uint64_t b1 = ZEROS ? ~H[w + 1] : H[w + 1];
+    const uint64_t b2 = ZEROS ? ~H[w + 2] : H[w + 2];
+    const uint32_t c1 = (uint32_t)__popcll(b1);
+    if (r < c1) {
+      b = b1;
+      w += 1;
+      break;
+    }
+    r -= c1;
+    b = b2;
+    w += 2;
+  }
+  return (w << 6) + nth_set_bit(b, (uint32_t)r);
+}
+
 __device__ __forceinline__ uint64_t ef_low(const EFDev& e, uint64_t i) {
   if (e.l == 0) return 0;
   const uint64_t bit = i * e.l;
@@ -60,32 +86,18 @@ __device__ __forceinline__ uint64_t ef_low(const EFDev& e, uint64_t i) {
 __device__ __forceinline__ uint64_t ef_one_pos(const EFDev& e, uint64_t i) {
   const uint64_t j = i >> e.lgq;
   const uint64_t p = e.S1[j];
-  uint64_t r = i - (j << e.lgq);
-  uint64_t w = p >> 6;
-  uint64_t b = e.H[w] & (~0ull << (p & 63));
-  while (true) {
-    const uint32_t c = (uint32_t)__popcll(b);
-    if (r < c) break;
-    r -= c;
-    b = e.H[++w];
-  }
-  return (w << 6) + nth_set_bit(b, (uint32_t)r);
+  const uint64_t r = i - (j << e.lgq);
+  const uint64_t w = p >> 6;
+  return ef_scan<false>(e.H, w, e.H[w] & (~0ull << (p & 63)), r);
 }
 
 // Position of zero number z (z < n_zeros).
 __device__ __forceinline__ uint64_t ef_zero_pos(const EFDev& e, uint64_t z) {
   const uint64_t j = z >> e.lgq;
   const uint64_t p = e.S0[j];
-  uint64_t r = z - (j << e.lgq);
-  uint64_t w = p >> 6;
-  uint64_t b = ~e.H[w] & (~0ull << (p & 63));
-  while (true) {
-    const uint32_t c = (uint32_t)__popcll(b);
-    if (r < c) break;
-    r -= c;
-    b = ~e.H[++w];
-  }
-  return (w << 6) + nth_set_bit(b, (uint32_t)r);
+  const uint64_t r = z - (j << e.lgq);
+  const uint64_t w = p >> 6;
+  return ef_scan<true>(e.H, w, ~e.H[w] & (~0ull << (p & 63)), r);
 }
 
 // select(i): the i-th smallest code (i < m).
@@ -198,16 +210,9 @@ __device__ __forceinline__ void ef_row(const EFDev& e, int32_t v, uint64_t* lo, 
     return;
   }
   // zero number hx1 - 1: the (hx1 - 1 - (hx0 ? hx0 : 0))-th zero from q (0-based)
-  uint64_t r = (hx1 - 1) - (hx0 > 0 ? hx0 : 0);
-  uint64_t w = q >> 6;
-  uint64_t b = ~e.H[w] & (~0ull << (q & 63));
-  while (true) {
-    const uint32_t c = (uint32_t)__popcll(b);
-    if (r < c) break;
-    r -= c;
-    b = ~e.H[++w];
-  }
-  const uint64_t p1 = (w << 6) + nth_set_bit(b, (uint32_t)r);
+  const uint64_t r = (hx1 - 1) - (hx0 > 0 ? hx0 : 0);
+  const uint64_t w = q >> 6;
+  const uint64_t p1 = ef_scan<true>(e.H, w, ~e.H[w] & (~0ull << (q & 63)), r);
   *d = (uint32_t)(p1 - (hx1 - 1) - i0);
 }
 
@@ -339,7 +344,7 @@ __device__ __forceinline__ void lane_walk_ef(const WalkArgs& a, const EFDev& e, 
       } else if (MODE == kEfFoW || (MODE == kEfRetW && t < 0)) {
         const uint64_t total = (uint64_t)R[lo + d - 1];
         if (total == 0) break;
-        j = upper_bound_gt(R + lo, d, scale_draw(r, total));
+        j = upper_bound_interp(R + lo, d, scale_draw(r, total), total);
       } else {
         const uint64_t tc = ((uint64_t)v << e.k) | (uint64_t)(uint32_t)t;
         const uint64_t rt = ef_rank(e, tc);
@@ -352,15 +357,10 @@ __device__ __forceinline__ void lane_walk_ef(const WalkArgs& a, const EFDev& e, 
         const uint64_t total = (uint64_t)kC16 * S + corr;
         if (total == 0) break;
         const uint64_t T = scale_draw(r, total);
-        uint32_t jl = 0, jh = d - 1;
-        while (jl < jh) {
-          const uint32_t mid = jl + ((jh - jl) >> 1);
-          const uint64_t Rm = (MODE == kEfRetW) ? (uint64_t)R[lo + mid] : (uint64_t)(mid + 1);
-          const uint64_t Bm = (uint64_t)kC16 * Rm + (mid >= pt ? corr : 0ull);
-          if (Bm > T) jh = mid;
-          else jl = mid + 1;
-        }
-        j = jl;
+        j = first_above_interp(d, T, total, [&](uint32_t m) -> uint64_t {
+          const uint64_t Rm = (MODE == kEfRetW) ? (uint64_t)R[lo + m] : (uint64_t)(m + 1);
+          return (uint64_t)kC16 * Rm + (m >= pt ? corr : 0ull);
+        });
       }
       const int32_t x = ef_nbr(e, lo + j);
       row[s] = x;
