@@ -144,6 +144,21 @@ def test_walks_powerlaw_and_ba():
     _walk_pair(O, D, W, np.arange(n), 1, 30, 9, 1024, oracle_rows=np.arange(0, n, 31))
 
 
+def test_walks_dense_rows():
+    """Rows spanning 2^(k - l) >= 64 buckets of high parts (a complete graph,
+    128 buckets, and mean degree about 47, 64 buckets: the walks take the
+    one-lane selects) and 32 buckets (mean degree about 25: the wavefront
+    keeps the rows' bucket boundaries in its lanes) give the CSR walks and the
+    oracle's."""
+    O, D, _ = synth.complete(80)
+    W = np.random.default_rng(3).integers(1, 60, size=len(D)).astype(np.uint32)
+    _walk_pair(O, D, W, np.arange(80), 4, 25, 5, 64, oracle_rows=np.arange(0, 320, 7))
+    for args in ((3000, 75000, 2.3, 50.0, 900.0), (3000, 40000, 2.3, 25.0, 600.0)):
+        O, D, W = synth.chung_lu(*args, (1, 100), seed=8)
+        n = len(O) - 1
+        _walk_pair(O, D, W, np.arange(n), 1, 25, 6, 256, oracle_rows=np.arange(0, n, 29))
+
+
 def test_negatives_and_handles_own_their_memory():
     O, D, W = synth.chung_lu(5000, 40000, 2.1, 12.0, 2000.0, (1, 100), seed=6)
     n = len(O) - 1
