@@ -980,6 +980,13 @@ PROFILE_SETS = {
              tuple(os.path.join(ROOT, "profiles", f) for f in (
                  "kernel_trace_chung_lu_1m_first_order.txt", "pmc_traffic_chung_lu_1m_first_order.txt",
                  "pmc_counters_chung_lu_1m_first_order.txt", "pmc_sectors_chung_lu_1m_first_order.txt"))),
+    "ef": ("k_walk_n2v_ef", 1, 1, "python3 /root/repo/bench.py --config ef --warmup 0 --steps {k}",
+           "1M-node Chung-Lu graph on the Elias-Fano store (quantum 256), node2vec (p, q) = (0.25, 4), one walk of "
+           "100 slots per node",
+           tuple(os.path.join(ROOT, "profiles", f) for f in (
+               "kernel_trace_ef_chung_lu_1m.txt", "pmc_traffic_ef_chung_lu_1m.txt", "pmc_counters_ef_chung_lu_1m.txt",
+               "pmc_sectors_ef_chung_lu_1m.txt")),
+           ("n2v_ef.hip", "n2v_device.hpp", "n2v_internal.hpp")),
     "big": ("k_walk_n2v", 1, 1, "python3 /root/repo/bench.py --config big --big-runs n2v --warmup 0 --steps {k} "
                                 "--cpu-seconds 0",
             "20M-node Chung-Lu graph, node2vec (p, q) = (1, 2), one walk of 80 slots per node",
@@ -996,7 +1003,8 @@ def summarize_kernel_profiles(which, root):
     tcc (profiles of the set's program) and cal_fetch, cal_write, cal_tcc
     (profiles of `bench.py --config calibrate`)."""
     import csv
-    KQ, n_trace, n_pmc, prog, title, files = PROFILE_SETS[which]
+    KQ, n_trace, n_pmc, prog, title, files = PROFILE_SETS[which][:6]
+    sources = PROFILE_SETS[which][6] if len(PROFILE_SETS[which]) > 6 else WALK_SOURCES
     trace_file, traffic_file, counters_file, sector_file = files
     cal = "python3 /root/repo/bench.py --config calibrate"
     cmd = "cd /tmp && rocprofv3 {what} --output-format csv -d <dir> -o run -- {prog}"
@@ -1014,7 +1022,7 @@ def summarize_kernel_profiles(which, root):
         "cal_tcc": cmd.format(what="--pmc " + " ".join(tcc_names), prog=cal),
     }
     sub = lambda k: os.path.join(root, k)  # noqa: E731
-    h = kernel_source_hash()
+    h = kernel_source_hash(sources)
     # kernel trace: stats table, and the timed launches' mean duration
     tr = _last_of(_dispatches(sub("trace")), KQ, n_trace)
     lines = [f"# rocprofv3 --kernel-trace --stats, {title}", f"# command: {cmds['trace']}", f"source_hash: {h}",
